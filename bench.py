@@ -1,0 +1,177 @@
+"""Throughput of the Force2Vec minibatch update on one MI355X.
+
+A step is one epoch of the paper's Algorithm 1 (random partition, per-batch
+shared negatives, per-vertex attraction and repulsion, the Eq. 10 step) over
+the whole synthetic graph.  Default workload: Chung-Lu power-law graph,
+n = 1,000,000, exponent 2.1, average degree 20; d = 128, sigmoid force,
+b = 384, s = 5, lr = 0.02, FP32; 1 warm-up epoch and 5 timed epochs.
+
+Prints one JSON line:
+  value      edge+negative updates per second = steps * (nnz + n s) / wall time
+  roofline   algorithmic HBM bytes of one epoch / the update kernel's average
+             duration (HIP events on the library's stream), against 8 TB/s
+  cpu_baseline  the FP64 oracle on the host cores over a bounded sample of the
+             same epoch (the first batches), in the same unit
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "cl1m": "Chung-Lu power-law graph n=1,000,000 gamma=2.1 avg degree 20 (symmetrised, no self-loops); "
+            "d=128, sigmoid force, batch 384, s=5 shared negatives, lr 0.02",
+    "er1k": "Erdos-Renyi n=1,024 avg degree 16; d=32, Student-t force, batch 256, s=5, lr 0.02 linear decay",
+    "sbm4m": "SBM n=4,000,000 in 64 blocks (c_in 24, c_out 6); d=128, BF16 rows + FP32 master, "
+             "Student-t force, batch 384, s=10, lr 0.02",
+    "rgg2m": "2-D random geometric graph n=2,000,000 avg degree 12; d=2, Student-t force, batch 384, s=5, lr 0.02",
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n: int, nnz: int, d: int, b: int, s: int, precision: str) -> int:
+    """HBM bytes one epoch must move: per stored edge its column index and the
+    neighbour's row; per vertex its row pointer, batch lookups, own row read
+    and new row written (plus the FP32 master in the bf16 form); per batch its
+    negative rows once."""
+    nb = (n + b - 1) // b
+    if precision == "bf16":
+        return nnz * (4 + 2 * d) + n * (10 * d + 12) + nb * s * 2 * d
+    return nnz * (4 + 4 * d) + n * (8 * d + 12) + nb * s * 4 * d
+
+
+def cpu_baseline(g, Z0, p, seconds_target: float = 12.0) -> dict:
+    """Time the FP64 oracle (as it stands) on the host over the first batches
+    of epoch 0, growing the sample until it takes about `seconds_target`."""
+    import oracle
+    op = oracle.OracleParams.from_dict(p)
+    Z = np.asarray(Z0, dtype=np.float64)
+    nb = (g.n + op.batch - 1) // op.batch
+    batches = 8
+    while True:
+        t0 = time.perf_counter()
+        _, pairs = oracle.epoch(g, Z, 0, op, return_pairs=True, batches=(0, min(batches, nb)))
+        dt = time.perf_counter() - t0
+        if dt >= seconds_target or batches >= nb:
+            break
+        batches = min(nb, int(batches * max(2.0, 1.2 * seconds_target / max(dt, 1e-3))))
+        log(f"cpu baseline: growing sample to {batches} batches")
+    return {"value": pairs / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {min(batches, nb)} of {nb} batches of epoch 0 ({pairs} pair updates, "
+                      f"{dt:.1f} s, FP64, OpenMP over the batch's vertices)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("only --gpus 1 is supported: the update is measured on one MI355X")
+        return 2
+    import torch
+    import graphgen as gg
+    import paper_2009_10035_amd as f2v
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        return 1
+    t0 = time.perf_counter()
+    g, p = gg.workload(args.workload)
+    log(f"graph {args.workload}: n={g.n} nnz={g.nnz} max degree={int(g.degrees().max())} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
+    dev = torch.device("cuda:0")
+    rowptr = torch.from_numpy(g.rowptr).to(dev)
+    colidx = torch.from_numpy(g.colidx).to(dev)
+    z = torch.from_numpy(Z0).to(dev)
+    params = f2v.make_params(g.n, g.nnz, p["d"], batch=p["batch"], s=p["s"], force=p["force"],
+                             precision=p["precision"], lr0=p["lr0"], lr_schedule=p["lr_schedule"],
+                             total_epochs=max(p["total_epochs"], args.warmup + args.steps),
+                             schedule=args.schedule, chunk=args.chunk or None, seed=p["seed"])
+    tr = f2v.Trainer(rowptr, colidx, z, params)
+    for e in range(args.warmup):
+        tr.epoch(e)
+    tr.check()
+    log(f"warm-up done ({args.warmup} epochs)")
+    torch.cuda.synchronize()
+    upd_ms = []
+    t_start = time.perf_counter()
+    for e in range(args.warmup, args.warmup + args.steps):
+        tr.epoch(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    tr.check()
+    # per-launch device time of the update kernel, from HIP events on the
+    # library's stream (separate pass so the timed loop has no host syncs)
+    for e in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
+        tr.epoch(e)
+        upd_ms.append(tr.last_epoch_ms())
+    tr.check()
+    loss = tr.loss()
+    log(f"timed {args.steps} epochs in {wall * 1e3:.2f} ms; loss {loss[0]:.6g}")
+    updates = g.nnz + g.n * p["s"]
+    value = args.steps * updates / wall
+    nbytes = algorithmic_bytes(g.n, g.nnz, p["d"], p["batch"], p["s"], p["precision"])
+    kern_ms = float(np.mean([u for u, _ in upd_ms]))
+    epoch_ms = float(np.mean([t for _, t in upd_ms]))
+    achieved = nbytes / (kern_ms * 1e-3) / 1e9
+    if args.copy_calibration:
+        nel = args.copy_calibration * (1 << 20) // 4
+        src = torch.empty(nel, dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB copied 3 times")
+    out = {
+        "metric": "edge+negative updates/sec at 1 MI355X",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if p["precision"] == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n": g.n, "nnz": g.nnz,
+                   "d": p["d"], "batch": p["batch"], "s": p["s"], "force": p["force"],
+                   "precision": p["precision"], "schedule": args.schedule,
+                   "updates_per_epoch": updates},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_update", "kernel_ms": kern_ms, "epoch_ms": epoch_ms,
+                     "algorithmic_bytes_per_launch": nbytes},
+        "loss_after": loss[0],
+    }
+    tr.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(g, Z0, p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,162 @@
+/*
+ * f2v.h -- C ABI of the MI355X Force2Vec minibatch update.
+ *
+ * The library trains a graph embedding Z (n x d) with the negative-sampling
+ * Force2Vec method: Algorithm 1 (epoch loop: random partition of the vertices
+ * into ceil(n/b) minibatches; per batch one shared set S_b of s uniform
+ * negative samples; gradient of every batch vertex; SGD step of Eq. 10 on the
+ * batch vertices only) driving Algorithm 2 (per-vertex gradient: attractive
+ * force over the CSR neighbours, Eq. 5 sigmoid or Eq. 8 Student-t, plus
+ * repulsive force over S_b, Eq. 6 or Eq. 9).  The semantics are the paper's
+ * synchronous minibatch SGD (Section 3.2): every gradient of batch k reads the
+ * embedding as left by batches 0..k-1, so the result does not depend on how
+ * the device schedules the work.
+ *
+ * Conventions
+ *  - Device pointers are HIP device memory owned by the caller, alive until
+ *    f2v_destroy.  The library allocates no device memory: all state lives in
+ *    the caller's workspace (size from f2v_workspace_size).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    asynchronous on that stream except f2v_init, f2v_loss, f2v_check and the
+ *    host-only queries.
+ *  - Every call returns f2v_status; no exception crosses the ABI.  On error
+ *    f2v_last_error(ctx) (or f2v_last_error(NULL) for calls without a context)
+ *    holds a message.
+ *  - Argument validation runs on the host before any HIP call.
+ *  - One host thread per context; distinct contexts are independent.
+ *
+ * Random streams (identical on every run and device; the epoch index is an
+ * argument, so a run resumed at epoch e equals an uninterrupted one):
+ *  - Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`.
+ *  - Partition of epoch e: position p -> vertex perm_e(p), a 12-round keyed
+ *    Feistel permutation of [0, 2^(2h)) (round r value Philox(e, r, R, 1).x0
+ *    masked to h bits) restricted to [0, n) by cycle walking; batch k holds
+ *    positions [k b, min(n, (k+1) b)).  F2V_PERM_IDENTITY uses perm_e(p) = p.
+ *  - Negatives of batch k in epoch e: S[k][j] = floor(w * n / 2^64) with w the
+ *    64-bit word x0:x1 of Philox(e, k, j, 2), j < s (uniform, with
+ *    replacement; u itself or a neighbour may be drawn).
+ *  - Loss negatives of vertex u: W[u][j] from Philox(u_lo, u_hi, j, 3).
+ */
+#ifndef F2V_H
+#define F2V_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    F2V_OK = 0,
+    F2V_E_INVALID_ARG = 1, /* a parameter or pointer is out of range */
+    F2V_E_BAD_GRAPH = 2,   /* CSR malformed: rowptr[0] != 0, decreasing rowptr,
+                              rowptr[n] != nnz, or a column index outside [0, n) */
+    F2V_E_OOM = 3,         /* workspace smaller than f2v_workspace_size */
+    F2V_E_HIP = 4,         /* a HIP runtime call failed */
+    F2V_E_STATE = 5,       /* call not valid in the context's state */
+    F2V_E_TIMEOUT = 6,     /* a device-side dependency wait exceeded its bound;
+                              the embedding is not valid after this */
+    F2V_E_BUSY = 7,        /* serving: no free slot or memory for the job */
+    F2V_E_UNSUPPORTED = 8  /* valid request this build does not implement */
+} f2v_status;
+
+typedef enum { F2V_FORCE_SIGMOID = 0, F2V_FORCE_STUDENT_T = 1 } f2v_force;
+typedef enum { F2V_FP32 = 0, F2V_BF16 = 1 } f2v_precision;
+typedef enum { F2V_LR_CONST = 0, F2V_LR_LINEAR = 1 } f2v_lr_schedule;
+typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
+/* Device scheduling of one epoch; both give bit-identical results.
+ * DATAFLOW: one persistent launch per epoch, batches overlap on the device and
+ *   a vertex row is read only once the batch that updates it has published it.
+ * STRICT: one launch per batch, batches separated by the stream order. */
+typedef enum { F2V_SCHED_DATAFLOW = 0, F2V_SCHED_STRICT = 1 } f2v_schedule;
+
+typedef struct {
+    int64_t n;            /* vertices, >= 1, < 2^31 */
+    int64_t nnz;          /* stored CSR entries (2m for a simple undirected graph) */
+    int32_t d;            /* embedding dimension: d % 4 == 0 up to 1024, d % 4 == 2
+                             up to 128, odd d up to 64 (BF16: even d only) */
+    int32_t batch;        /* minibatch size b >= 1 */
+    int32_t s;            /* shared negatives per batch, 0..64 */
+    int32_t force;        /* f2v_force */
+    int32_t precision;    /* f2v_precision */
+    int32_t lr_schedule;  /* f2v_lr_schedule: eta_e = lr0 or lr0 (1 - e / total_epochs) */
+    float lr0;            /* initial step size eta > 0 (the paper uses 0.02) */
+    float eps;            /* Student-t repulsion regulariser, 0 <= eps < 1: the
+                             repulsive force is the gradient of
+                             log(1+q) - log(q+eps), q = |z_u - z_w|^2; eps = 0 is
+                             Eq. 9 exactly (taken as 0 at q = 0) */
+    int32_t total_epochs; /* E of the linear schedule (>= 1 if linear) */
+    int32_t perm_mode;    /* f2v_perm_mode */
+    int32_t schedule;     /* f2v_schedule */
+    int32_t chunk;        /* neighbours per work unit; rows of higher degree are
+                             split into several units whose partial sums are
+                             combined in a fixed order.  0 = default (128). */
+    uint64_t seed;        /* key of every random stream */
+} f2v_params;
+
+typedef struct f2v_ctx f2v_ctx;
+
+/* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
+ * eps = 1e-3, random partition, dataflow schedule, chunk 128, seed 0.
+ * n, nnz and d must still be set. */
+void f2v_default_params(f2v_params *p);
+
+/* Host only.  Bytes of device workspace the context needs (a bound from
+ * n, nnz, d, b, s, precision and chunk; independent of the graph's degrees). */
+f2v_status f2v_workspace_size(const f2v_params *p, size_t *bytes);
+
+/* Create a context on the current HIP device.
+ *   d_rowptr : int64[n+1] CSR row offsets (device)
+ *   d_colidx : int32[nnz] column indices (device); row u lists N(u)
+ *   d_z      : float[n*d] row-major initial embedding (device, in/out).  FP32:
+ *              the library alternates between d_z and a workspace copy;
+ *              f2v_sync_embedding makes d_z current.  BF16: d_z holds the FP32
+ *              master rows and is updated in place; bf16 copies feed the forces.
+ *   d_ws, ws_bytes : workspace (device, >= f2v_workspace_size bytes, 256-byte aligned)
+ * Validates the CSR on the device and synchronises the stream once. */
+f2v_status f2v_init(const f2v_params *p, const int64_t *d_rowptr, const int32_t *d_colidx,
+                    float *d_z, void *d_ws, size_t ws_bytes, void *stream, f2v_ctx **out);
+
+/* One epoch of Algorithm 1 with epoch index `epoch` (>= 0): partition,
+ * negatives, and the ceil(n/b) batch updates.  Asynchronous.  The result
+ * depends only on the current embedding, the epoch index and the params. */
+f2v_status f2v_epoch(f2v_ctx *ctx, int32_t epoch);
+
+/* Loss of Eq. 2 on the current embedding, with s fixed loss negatives per
+ * vertex (W above): out[0] = total, out[1] = attractive, out[2] = repulsive.
+ * Per-pair terms in FP32, sums in FP64 in a fixed order.  BF16: evaluated on
+ * the bf16 rows the forces read.  Synchronises the stream. */
+f2v_status f2v_loss(f2v_ctx *ctx, double out[3]);
+
+/* Make d_z hold the current embedding (FP32: a device copy if the current
+ * buffer is the workspace one).  Asynchronous. */
+f2v_status f2v_sync_embedding(f2v_ctx *ctx);
+
+/* Synchronise the stream and report a device-side error raised since the
+ * last check (F2V_E_TIMEOUT for an exceeded dependency wait). */
+f2v_status f2v_check(f2v_ctx *ctx);
+
+/* Release the context (no device memory to free; the caller owns it). */
+f2v_status f2v_destroy(f2v_ctx *ctx);
+
+const char *f2v_status_string(f2v_status st);
+const char *f2v_last_error(const f2v_ctx *ctx);
+
+/* Device copies of the random streams an epoch uses, for checking them.
+ *   f2v_partition : d_perm int32[n], perm_e(p) for every position p
+ *   f2v_negatives : d_S int32[ceil(n/b) * s], S[k][j] at k*s + j
+ * Asynchronous on `stream`. */
+f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_mode,
+                         int32_t *d_perm, void *stream);
+f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch,
+                         int32_t *d_S, void *stream);
+
+/* Device time of the most recent f2v_epoch's update kernel(s) in ms, measured
+ * with HIP events on the context's stream (prologue excluded).  Synchronises. */
+f2v_status f2v_last_epoch_ms(f2v_ctx *ctx, float *update_ms, float *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* F2V_H */

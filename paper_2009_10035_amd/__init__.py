@@ -1,0 +1,114 @@
+"""MI355X-native Force2Vec minibatch update (arXiv:2009.10035).
+
+`Trainer` drives the C ABI of libf2v.so: f2v_init on a CSR graph and an
+initial embedding held in torch device tensors, f2v_epoch per epoch of the
+paper's Algorithm 1, f2v_loss for the Eq. 2 loss.  There is no CPU fallback:
+without the HIP library and a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._binding import (EXPORTS, F2VError, Params, check, load, make_params, workspace_size)
+
+__all__ = ["Trainer", "F2VError", "Params", "make_params", "workspace_size", "partition",
+           "negatives", "load", "EXPORTS"]
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_device(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Trainer:
+    """One embedding run on one device.
+
+    rowptr: int64 [n+1], colidx: int32 [nnz], z: float32 [n, d] (all on the
+    device; z is the FP32 embedding, or the FP32 master rows in the bf16 form).
+    The tensors must stay alive as long as the trainer.
+    """
+
+    def __init__(self, rowptr: torch.Tensor, colidx: torch.Tensor, z: torch.Tensor, params: Params):
+        _require_device(rowptr, torch.int64, "rowptr")
+        _require_device(colidx, torch.int32, "colidx")
+        _require_device(z, torch.float32, "z")
+        if z.dim() != 2 or z.shape[0] != params.n or z.shape[1] != params.d:
+            raise ValueError("z must have shape (n, d)")
+        if rowptr.numel() != params.n + 1 or colidx.numel() != params.nnz:
+            raise ValueError("rowptr/colidx sizes do not match n/nnz")
+        self.lib = load()
+        self.params = params
+        self.device = z.device
+        self.rowptr, self.colidx, self.z = rowptr, colidx, z
+        nbytes = workspace_size(params)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=z.device)
+        self.ctx = ctypes.c_void_p()
+        empty = torch.empty(1, dtype=torch.int32, device=z.device)
+        self._empty = empty
+        col_ptr = colidx.data_ptr() if colidx.numel() > 0 else empty.data_ptr()
+        check(self.lib.f2v_init(ctypes.byref(params), rowptr.data_ptr(), col_ptr, z.data_ptr(),
+                                self.workspace.data_ptr(), nbytes, _stream_handle(z.device),
+                                ctypes.byref(self.ctx)))
+
+    def epoch(self, e: int) -> None:
+        check(self.lib.f2v_epoch(self.ctx, int(e)), self.ctx)
+
+    def run(self, epochs: int, first: int = 0) -> None:
+        for e in range(first, first + epochs):
+            self.epoch(e)
+
+    def loss(self):
+        out = (ctypes.c_double * 3)()
+        check(self.lib.f2v_loss(self.ctx, out), self.ctx)
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def sync_embedding(self) -> torch.Tensor:
+        """Make `z` hold the current embedding (FP32 master in the bf16 form)."""
+        check(self.lib.f2v_sync_embedding(self.ctx), self.ctx)
+        return self.z
+
+    def check(self) -> None:
+        check(self.lib.f2v_check(self.ctx), self.ctx)
+
+    def last_epoch_ms(self):
+        u, t = ctypes.c_float(0), ctypes.c_float(0)
+        check(self.lib.f2v_last_epoch_ms(self.ctx, ctypes.byref(u), ctypes.byref(t)), self.ctx)
+        return float(u.value), float(t.value)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.f2v_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def partition(n: int, seed: int, epoch: int, mode: str = "random", device="cuda") -> torch.Tensor:
+    """perm_e on the device (int32 [n])."""
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    check(load().f2v_partition(n, seed, epoch, 1 if mode == "identity" else 0, out.data_ptr(),
+                               _stream_handle(out.device)))
+    return out
+
+
+def negatives(n: int, batch: int, s: int, seed: int, epoch: int, device="cuda") -> torch.Tensor:
+    """S[k, j] of every batch of the epoch on the device (int32 [nb, s])."""
+    nb = (n + batch - 1) // batch
+    out = torch.empty((nb, max(s, 0)), dtype=torch.int32, device=device)
+    ptr = out.data_ptr() if out.numel() else 0
+    check(load().f2v_negatives(n, batch, s, seed, epoch, ptr, _stream_handle(out.device)))
+    return out

@@ -1,0 +1,495 @@
+// Host side of the C ABI declared in include/f2v.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/f2v.h"
+#include "f2v_device.h"
+#include "f2v_kernels.h"
+
+using f2v::EpochArgs;
+using f2v::LossArgs;
+using f2v::SetupArgs;
+using f2v::Variant;
+
+namespace {
+
+constexpr int kDefaultChunk = 128;
+constexpr int kMaxChunk = 1 << 20;
+constexpr int kBlock = 256;
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+thread_local std::string g_error;
+
+struct Layout {
+  size_t zbuf1, bbuf0, bbuf1, perm, bid, ucnt, uoff, negs, btot, breal, bstart, ngroups, tmap,
+      stamp, hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part,
+      loss_out, total;
+  int64_t nb, tmap_cap, hub_slot_cap;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int32_t chunk_of(const f2v_params& p) { return p.chunk > 0 ? p.chunk : kDefaultChunk; }
+
+Layout layout_of(const f2v_params& p) {
+  Layout L{};
+  const int64_t n = p.n, d = p.d;
+  const int32_t chunk = chunk_of(p);
+  L.nb = (n + p.batch - 1) / p.batch;
+  // a split row of degree deg > chunk has ceil(deg/chunk) < 2 deg / chunk units
+  L.hub_slot_cap = 2 * (p.nnz / chunk) + 1;
+  // tickets: one per unit, plus at most 63 padding tickets per batch
+  L.tmap_cap = n + p.nnz / chunk + L.nb * 63 + 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  const bool bf16 = p.precision == F2V_BF16;
+  L.zbuf1 = take(bf16 ? 0 : size_t(n) * d * sizeof(float));
+  L.bbuf0 = take(bf16 ? size_t(n) * d * 2 : 0);
+  L.bbuf1 = take(bf16 ? size_t(n) * d * 2 : 0);
+  L.perm = take(size_t(n) * 4);
+  L.bid = take(size_t(n) * 4);
+  L.ucnt = take(size_t(n) * 4);
+  L.uoff = take(size_t(n) * 4);
+  L.negs = take(size_t(L.nb) * (p.s > 0 ? p.s : 1) * 4);
+  L.btot = take(size_t(L.nb) * 4);
+  L.breal = take(size_t(L.nb) * 4);
+  L.bstart = take(size_t(L.nb + 1) * 4);
+  L.ngroups = take(4);
+  L.tmap = take(size_t(L.tmap_cap) * 8);
+  L.stamp = take(size_t(n) * 4);
+  L.hub_base = take(size_t(n) * 8);
+  L.hub_cnt = take(size_t(n) * 4);
+  L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
+  L.err = take(4);
+  L.csr_flag = take(4);
+  L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
+  L.scan_total = take(8);
+  L.loss_part = take(size_t(n) * 16);
+  L.loss_out = take(3 * 8);
+  L.total = off;
+  return L;
+}
+
+f2v_status fail(std::string* where, f2v_status st, const std::string& msg) {
+  if (where) *where = msg;
+  g_error = msg;
+  return st;
+}
+
+f2v_status validate(const f2v_params* p, std::string* msg) {
+  if (!p) return fail(msg, F2V_E_INVALID_ARG, "params is NULL");
+  if (p->n < 1 || p->n >= (int64_t{1} << 31) - 1)
+    return fail(msg, F2V_E_INVALID_ARG, "n must be in [1, 2^31 - 1)");
+  if (p->nnz < 0 || p->nnz >= (int64_t{1} << 40)) return fail(msg, F2V_E_INVALID_ARG, "nnz out of range");
+  if (p->d < 1 || p->d > 1024) return fail(msg, F2V_E_INVALID_ARG, "d must be in [1, 1024]");
+  if (p->precision != F2V_FP32 && p->precision != F2V_BF16)
+    return fail(msg, F2V_E_INVALID_ARG, "precision must be F2V_FP32 or F2V_BF16");
+  if (!f2v::find_variant(p->d, p->precision == F2V_BF16))
+    return fail(msg, F2V_E_UNSUPPORTED,
+                "unsupported d=" + std::to_string(p->d) +
+                    " (d % 4 == 0 up to 1024, d % 4 == 2 up to 128, odd d up to 64; bf16 even d)");
+  if (p->batch < 1) return fail(msg, F2V_E_INVALID_ARG, "batch must be >= 1");
+  if (p->s < 0 || p->s > 64) return fail(msg, F2V_E_INVALID_ARG, "s must be in [0, 64]");
+  if (p->force != F2V_FORCE_SIGMOID && p->force != F2V_FORCE_STUDENT_T)
+    return fail(msg, F2V_E_INVALID_ARG, "force must be sigmoid or Student-t");
+  if (!std::isfinite(p->lr0) || !(p->lr0 > 0.0f)) return fail(msg, F2V_E_INVALID_ARG, "lr0 must be finite and > 0");
+  if (!std::isfinite(p->eps) || p->eps < 0.0f || p->eps >= 1.0f)
+    return fail(msg, F2V_E_INVALID_ARG, "eps must be in [0, 1)");
+  if (p->lr_schedule != F2V_LR_CONST && p->lr_schedule != F2V_LR_LINEAR)
+    return fail(msg, F2V_E_INVALID_ARG, "lr_schedule must be const or linear");
+  if (p->lr_schedule == F2V_LR_LINEAR && p->total_epochs < 1)
+    return fail(msg, F2V_E_INVALID_ARG, "linear schedule needs total_epochs >= 1");
+  if (p->perm_mode != F2V_PERM_RANDOM && p->perm_mode != F2V_PERM_IDENTITY)
+    return fail(msg, F2V_E_INVALID_ARG, "perm_mode must be random or identity");
+  if (p->schedule != F2V_SCHED_DATAFLOW && p->schedule != F2V_SCHED_STRICT)
+    return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow or strict");
+  if (p->chunk < 0 || p->chunk > kMaxChunk) return fail(msg, F2V_E_INVALID_ARG, "chunk must be in [0, 2^20]");
+  const Layout L = layout_of(*p);
+  if (L.tmap_cap >= (int64_t{1} << 31)) return fail(msg, F2V_E_INVALID_ARG, "too many work units for int32 tickets");
+  return F2V_OK;
+}
+
+}  // namespace
+
+struct f2v_ctx {
+  f2v_params p{};
+  Layout L{};
+  hipStream_t stream = nullptr;
+  const int64_t* rowptr = nullptr;
+  const int32_t* colidx = nullptr;
+  float* z_user = nullptr;
+  char* ws = nullptr;
+  float* zbuf[2] = {nullptr, nullptr};
+  uint16_t* bbuf[2] = {nullptr, nullptr};
+  int cur = 0;
+  uint32_t gen = 0;
+  const Variant* var = nullptr;
+  int update_grid = 0;
+  int cus = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  bool timed = false;
+  std::string err;
+
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+#define HIP_TRY(ctx, call)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail((ctx) ? &(ctx)->err : nullptr, F2V_E_HIP,                                     \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                           \
+  } while (0)
+
+int slots_of(const Variant* v) { return 64 / v->g; }
+
+float epoch_lr(const f2v_params& p, int32_t e) {
+  double lr = p.lr0;
+  if (p.lr_schedule == F2V_LR_LINEAR) lr = double(p.lr0) * (1.0 - double(e) / double(p.total_epochs));
+  return static_cast<float>(lr);
+}
+
+}  // namespace
+
+extern "C" {
+
+void f2v_default_params(f2v_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->batch = 384;
+  p->s = 5;
+  p->force = F2V_FORCE_SIGMOID;
+  p->precision = F2V_FP32;
+  p->lr_schedule = F2V_LR_CONST;
+  p->lr0 = 0.02f;
+  p->eps = 1e-3f;
+  p->total_epochs = 1;
+  p->perm_mode = F2V_PERM_RANDOM;
+  p->schedule = F2V_SCHED_DATAFLOW;
+  p->chunk = kDefaultChunk;
+  p->seed = 0;
+}
+
+f2v_status f2v_workspace_size(const f2v_params* p, size_t* bytes) {
+  f2v_status st = validate(p, nullptr);
+  if (st != F2V_OK) return st;
+  if (!bytes) return fail(nullptr, F2V_E_INVALID_ARG, "bytes is NULL");
+  *bytes = layout_of(*p).total;
+  return F2V_OK;
+}
+
+const char* f2v_status_string(f2v_status st) {
+  switch (st) {
+    case F2V_OK: return "ok";
+    case F2V_E_INVALID_ARG: return "invalid argument";
+    case F2V_E_BAD_GRAPH: return "malformed CSR graph";
+    case F2V_E_OOM: return "workspace too small";
+    case F2V_E_HIP: return "HIP runtime error";
+    case F2V_E_STATE: return "invalid state";
+    case F2V_E_TIMEOUT: return "device dependency wait timed out";
+    case F2V_E_BUSY: return "busy";
+    case F2V_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* f2v_last_error(const f2v_ctx* ctx) { return ctx ? ctx->err.c_str() : g_error.c_str(); }
+
+f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
+                    void* d_ws, size_t ws_bytes, void* stream, f2v_ctx** out) {
+  f2v_status st = validate(p, nullptr);
+  if (st != F2V_OK) return st;
+  if (!out) return fail(nullptr, F2V_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d_rowptr || !d_z || !d_ws || (p->nnz > 0 && !d_colidx))
+    return fail(nullptr, F2V_E_INVALID_ARG, "NULL device pointer");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+    return fail(nullptr, F2V_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(d_z) & 15) != 0)
+    return fail(nullptr, F2V_E_INVALID_ARG, "embedding must be 16-byte aligned");
+  const Layout L = layout_of(*p);
+  if (ws_bytes < L.total)
+    return fail(nullptr, F2V_E_OOM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                        std::to_string(L.total));
+  f2v_ctx* c = new (std::nothrow) f2v_ctx();
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "host allocation failed");
+  c->p = *p;
+  if (c->p.chunk == 0) c->p.chunk = kDefaultChunk;
+  c->L = L;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->rowptr = d_rowptr;
+  c->colidx = d_colidx;
+  c->z_user = d_z;
+  c->ws = static_cast<char*>(d_ws);
+  c->var = f2v::find_variant(p->d, p->precision == F2V_BF16);
+  const bool bf16 = p->precision == F2V_BF16;
+  c->zbuf[0] = d_z;
+  c->zbuf[1] = bf16 ? nullptr : c->at<float>(L.zbuf1);
+  c->bbuf[0] = bf16 ? c->at<uint16_t>(L.bbuf0) : nullptr;
+  c->bbuf[1] = bf16 ? c->at<uint16_t>(L.bbuf1) : nullptr;
+
+  auto bail = [&](f2v_status s, const std::string& m) {
+    g_error = m;
+    for (hipEvent_t& e : c->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete c;
+    return s;
+  };
+  hipError_t he;
+  int dev = 0;
+  if ((he = hipGetDevice(&dev)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  if ((he = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
+  int per_cu = 0;
+  if ((he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->var->update, kBlock, 0)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("occupancy query: ") + hipGetErrorString(he));
+  if (const char* env = std::getenv("F2V_UPDATE_BLOCKS_PER_CU")) {
+    const int want = std::atoi(env);
+    if (want >= 1 && want < per_cu) per_cu = want;
+  }
+  if (per_cu < 1) per_cu = 1;
+  c->update_grid = per_cu * c->cus;
+  for (hipEvent_t& e : c->ev)
+    if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+
+  uint32_t* flag = c->at<uint32_t>(L.csr_flag);
+  uint32_t* errw = c->at<uint32_t>(L.err);
+  const hipStream_t s = c->stream;
+  if ((he = f2v::launch_fill_u32(flag, 0u, 1, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(errw, 0u, 1, s)) != hipSuccess ||
+      (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
+      (he = hipStreamSynchronize(s)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("CSR check: ") + hipGetErrorString(he));
+  uint32_t hflag = 0;
+  if ((he = hipMemcpy(&hflag, flag, 4, hipMemcpyDeviceToHost)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("CSR check copy: ") + hipGetErrorString(he));
+  if (hflag != 0) {
+    std::string m = "malformed CSR:";
+    if (hflag & 1u) m += " rowptr[0] != 0;";
+    if (hflag & 2u) m += " rowptr decreases;";
+    if (hflag & 4u) m += " rowptr[n] != nnz;";
+    if (hflag & 8u) m += " column index outside [0, n);";
+    return bail(F2V_E_BAD_GRAPH, m);
+  }
+  int64_t hub_total = 0;
+  if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.hub_base),
+                                 c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.stamp), 0u, p->n, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, p->n, s)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
+  if (bf16 && (he = f2v::launch_to_bf16(d_z, c->bbuf[0], p->n * int64_t(p->d), s)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("bf16 copy: ") + hipGetErrorString(he));
+  if ((he = hipStreamSynchronize(s)) != hipSuccess ||
+      (he = hipMemcpy(&hub_total, c->at<int64_t>(L.scan_total), 8, hipMemcpyDeviceToHost)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("init sync: ") + hipGetErrorString(he));
+  if (hub_total > L.hub_slot_cap) return bail(F2V_E_INVALID_ARG, "split-row slots exceed the workspace bound");
+  *out = c;
+  return F2V_OK;
+}
+
+f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (epoch < 0) return fail(&c->err, F2V_E_INVALID_ARG, "epoch must be >= 0");
+  const f2v_params& p = c->p;
+  const Layout& L = c->L;
+  const hipStream_t s = c->stream;
+  const bool bf16 = p.precision == F2V_BF16;
+  const int slots = slots_of(c->var);
+  if (++c->gen == 0) {  // generations never repeat: restart the stamps after a wrap
+    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(L.stamp), 0u, p.n, s));
+    c->gen = 1;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[0], s));
+
+  SetupArgs sa{};
+  sa.rowptr = c->rowptr;
+  sa.perm = c->at<int32_t>(L.perm);
+  sa.bid = c->at<int32_t>(L.bid);
+  sa.ucnt = c->at<int32_t>(L.ucnt);
+  sa.uoff = c->at<int32_t>(L.uoff);
+  sa.negs = c->at<int32_t>(L.negs);
+  sa.btot = c->at<int32_t>(L.btot);
+  sa.breal = c->at<int32_t>(L.breal);
+  sa.bstart = c->at<int32_t>(L.bstart);
+  sa.tmap = c->at<int2>(L.tmap);
+  sa.ngroups = c->at<int32_t>(L.ngroups);
+  sa.n = p.n;
+  sa.b = p.batch;
+  sa.s = p.s;
+  sa.nb = static_cast<int32_t>(L.nb);
+  sa.chunk = p.chunk;
+  sa.slots = slots;
+  sa.seed = p.seed;
+  sa.epoch = static_cast<uint32_t>(epoch);
+  sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
+  const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
+  sa.feistel_half = f.half;
+  sa.feistel_mask = f.mask;
+  HIP_TRY(c, f2v::launch_setup(sa, s));
+
+  EpochArgs A{};
+  A.rowptr = c->rowptr;
+  A.colidx = c->colidx;
+  if (bf16) {
+    A.zc = c->bbuf[c->cur];
+    A.zn = c->bbuf[1 - c->cur];
+    A.master = c->z_user;
+  } else {
+    A.zc = c->zbuf[c->cur];
+    A.zn = c->zbuf[1 - c->cur];
+    A.master = nullptr;
+  }
+  A.perm = sa.perm;
+  A.bid = sa.bid;
+  A.ucnt = sa.ucnt;
+  A.negs = sa.negs;
+  A.tmap = sa.tmap;
+  A.bstart = sa.bstart;
+  A.ngroups = sa.ngroups;
+  A.stamp = c->at<uint32_t>(L.stamp);
+  A.hub_base = c->at<int64_t>(L.hub_base);
+  A.hub_cnt = c->at<uint32_t>(L.hub_cnt);
+  A.hub_part = c->at<float>(L.hub_part);
+  A.err = c->at<uint32_t>(L.err);
+  A.n = p.n;
+  A.d = p.d;
+  A.b = p.batch;
+  A.s = p.s;
+  A.nb = static_cast<int32_t>(L.nb);
+  A.chunk = p.chunk;
+  A.force = p.force;
+  A.lr = epoch_lr(p, epoch);
+  A.eps = p.eps;
+  A.gen = c->gen;
+  A.spin_limit = kSpinLimit;
+  HIP_TRY(c, hipEventRecord(c->ev[1], s));
+  if (p.schedule == F2V_SCHED_DATAFLOW) {
+    A.strict_batch = -1;
+    void* args[] = {&A};
+    HIP_TRY(c, hipLaunchCooperativeKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+  } else {
+    const int64_t groups_hint = (p.batch + slots - 1) / slots;
+    int grid = static_cast<int>((groups_hint + 3) / 4);
+    if (grid < 1) grid = 1;
+    if (grid > c->update_grid) grid = c->update_grid;
+    for (int64_t k = 0; k < L.nb; ++k) {
+      A.strict_batch = static_cast<int32_t>(k);
+      void* args[] = {&A};
+      HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(grid), dim3(kBlock), args, 0, s));
+    }
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[2], s));
+  c->timed = true;
+  c->cur = 1 - c->cur;
+  return F2V_OK;
+}
+
+f2v_status f2v_last_epoch_ms(f2v_ctx* c, float* update_ms, float* total_ms) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (!c->timed) return fail(&c->err, F2V_E_STATE, "no epoch has run");
+  HIP_TRY(c, hipEventSynchronize(c->ev[2]));
+  float u = 0.f, t = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&u, c->ev[1], c->ev[2]));
+  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[2]));
+  if (update_ms) *update_ms = u;
+  if (total_ms) *total_ms = t;
+  return F2V_OK;
+}
+
+f2v_status f2v_check(f2v_ctx* c) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint32_t e = 0;
+  HIP_TRY(c, hipMemcpy(&e, c->at<uint32_t>(c->L.err), 4, hipMemcpyDeviceToHost));
+  if (e != 0) {
+    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, 1, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return fail(&c->err, F2V_E_TIMEOUT, "a device dependency wait exceeded its bound");
+  }
+  return F2V_OK;
+}
+
+f2v_status f2v_loss(f2v_ctx* c, double out[3]) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(&c->err, F2V_E_INVALID_ARG, "out is NULL");
+  const f2v_params& p = c->p;
+  LossArgs A{};
+  A.rowptr = c->rowptr;
+  A.colidx = c->colidx;
+  A.z = p.precision == F2V_BF16 ? static_cast<const void*>(c->bbuf[c->cur])
+                                : static_cast<const void*>(c->zbuf[c->cur]);
+  A.part = c->at<double>(c->L.loss_part);
+  A.out = c->at<double>(c->L.loss_out);
+  A.n = p.n;
+  A.d = p.d;
+  A.s = p.s;
+  A.force = p.force;
+  A.eps = p.eps;
+  A.seed = p.seed;
+  const int slots = slots_of(c->var);
+  int64_t blocks = (p.n + int64_t(slots) * 4 - 1) / (int64_t(slots) * 4);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  void* args[] = {&A};
+  HIP_TRY(c, hipLaunchKernel(c->var->loss, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), args, 0, c->stream));
+  HIP_TRY(c, f2v::launch_loss_reduce(A, c->stream));
+  double h[3];
+  HIP_TRY(c, hipMemcpyAsync(h, A.out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  out[0] = h[0];
+  out[1] = h[1];
+  out[2] = h[2];
+  return F2V_OK;
+}
+
+f2v_status f2v_sync_embedding(f2v_ctx* c) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (c->p.precision == F2V_FP32 && c->cur != 0) {
+    HIP_TRY(c, hipMemcpyAsync(c->zbuf[0], c->zbuf[c->cur], size_t(c->p.n) * c->p.d * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+    c->cur = 0;
+  }
+  return F2V_OK;
+}
+
+f2v_status f2v_destroy(f2v_ctx* c) {
+  if (!c) return F2V_OK;
+  for (hipEvent_t& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return F2V_OK;
+}
+
+f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_mode, int32_t* d_perm,
+                         void* stream) {
+  if (n < 1 || n >= (int64_t{1} << 31) - 1) return fail(nullptr, F2V_E_INVALID_ARG, "n out of range");
+  if (epoch < 0) return fail(nullptr, F2V_E_INVALID_ARG, "epoch must be >= 0");
+  if (perm_mode != F2V_PERM_RANDOM && perm_mode != F2V_PERM_IDENTITY)
+    return fail(nullptr, F2V_E_INVALID_ARG, "perm_mode must be random or identity");
+  if (!d_perm) return fail(nullptr, F2V_E_INVALID_ARG, "d_perm is NULL");
+  hipError_t e = f2v::launch_partition(n, seed, static_cast<uint32_t>(epoch), perm_mode == F2V_PERM_IDENTITY,
+                                       d_perm, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("partition: ") + hipGetErrorString(e));
+  return F2V_OK;
+}
+
+f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch, int32_t* d_S,
+                         void* stream) {
+  if (n < 1 || n >= (int64_t{1} << 31) - 1) return fail(nullptr, F2V_E_INVALID_ARG, "n out of range");
+  if (batch < 1 || s < 0 || s > 64 || epoch < 0) return fail(nullptr, F2V_E_INVALID_ARG, "bad batch, s or epoch");
+  if (!d_S && s > 0) return fail(nullptr, F2V_E_INVALID_ARG, "d_S is NULL");
+  hipError_t e = f2v::launch_negatives(n, batch, s, seed, static_cast<uint32_t>(epoch), d_S,
+                                       static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("negatives: ") + hipGetErrorString(e));
+  return F2V_OK;
+}
+
+}  // extern "C"

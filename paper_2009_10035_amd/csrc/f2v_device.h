@@ -1,0 +1,269 @@
+// Device building blocks of the Force2Vec update for gfx950: the random
+// streams, coherent row access across XCDs, lane-group reductions and the
+// per-pair forces.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace f2v {
+
+// ---------------------------------------------------------------------------
+// Random streams.  Philox4x32-10 (Salmon et al., SC'11): ten rounds; each
+// round takes the 64-bit products of counter words 0 and 2 with two odd
+// multipliers, returns their low halves as words 3 and 1 and their high halves
+// xor-ed with the other counter word and the round key as words 2 and 0; the
+// key advances by two Weyl increments per round.
+enum : uint32_t { kTagPerm = 1, kTagNeg = 2, kTagEval = 3 };
+constexpr int kFeistelRounds = 12;
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint64_t seed) {
+  uint32_t k0 = static_cast<uint32_t>(seed);
+  uint32_t k1 = static_cast<uint32_t>(seed >> 32);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo_a = 0xD2511F53u * c0, hi_a = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo_b = 0xCD9E8D57u * c2, hi_b = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi_b ^ c1 ^ k0;
+    c2 = hi_a ^ c3 ^ k1;
+    c1 = lo_b;
+    c3 = lo_a;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// floor(w * n / 2^64) for the 64-bit word w = hi:lo -- uniform on [0, n).
+__device__ __forceinline__ int32_t uniform_index(uint32_t hi, uint32_t lo, int64_t n) {
+  const uint64_t w = (static_cast<uint64_t>(hi) << 32) | lo;
+  return static_cast<int32_t>(__umul64hi(w, static_cast<uint64_t>(n)));
+}
+
+// Keyed pseudo-random permutation of [0, n): a balanced Feistel network on
+// 2h bits, iterated (cycle walking) until the value falls inside [0, n).
+struct Feistel {
+  uint64_t seed;
+  uint32_t epoch;
+  int32_t half;  // h
+  uint32_t mask; // 2^h - 1
+  int64_t n;
+};
+
+__host__ inline Feistel make_feistel(int64_t n, uint64_t seed, uint32_t epoch) {
+  int bits = 2;
+  while ((int64_t{1} << bits) < n) ++bits;
+  bits += bits & 1;
+  Feistel f{seed, epoch, bits / 2, (1u << (bits / 2)) - 1u, n};
+  return f;
+}
+
+__device__ __forceinline__ uint32_t feistel_round(const Feistel& f, uint32_t r, uint32_t x) {
+  return philox(f.epoch, r, x, kTagPerm, f.seed).x & f.mask;
+}
+
+__device__ inline int32_t feistel_permute(const Feistel& f, int64_t p) {
+  uint64_t x = static_cast<uint64_t>(p);
+  do {
+    uint32_t hi = static_cast<uint32_t>(x >> f.half), lo = static_cast<uint32_t>(x) & f.mask;
+    for (uint32_t r = 0; r < kFeistelRounds; ++r) {
+      const uint32_t mixed = hi ^ feistel_round(f, r, lo);
+      hi = lo;
+      lo = mixed;
+    }
+    x = (static_cast<uint64_t>(hi) << f.half) | lo;
+  } while (x >= static_cast<uint64_t>(f.n));
+  return static_cast<int32_t>(x);
+}
+
+// ---------------------------------------------------------------------------
+// Memory access.  Rows of the next-epoch buffer are written by one wave and
+// read by waves on other XCDs while the kernel runs; the per-XCD L2 caches are
+// not coherent with each other, so these accesses carry device scope (sc1)
+// and bypass stale L2 copies.  Ordering is given by waiting for the stores'
+// completion (vmcnt) before the publishing stamp store.
+__device__ __forceinline__ uint32_t ld_coherent_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_coherent_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory operation this wave issued has completed, and keep
+// the compiler from moving memory operations across the wait.
+__device__ __forceinline__ void drain_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+// Round to nearest, ties to even; NaN stays NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Element type of the rows the forces read.
+template <bool BF16> struct Elem;
+template <> struct Elem<false> { using T = float; };
+template <> struct Elem<true> { using T = uint16_t; };
+
+// V consecutive elements starting at `p` (V * sizeof(T)-aligned) as floats.
+template <int V, bool BF16>
+__device__ __forceinline__ void load_plain(const typename Elem<BF16>::T* p, float* out) {
+  if constexpr (!BF16) {
+    if constexpr (V == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      out[0] = t.x; out[1] = t.y; out[2] = t.z; out[3] = t.w;
+    } else if constexpr (V == 2) {
+      const float2 t = *reinterpret_cast<const float2*>(p);
+      out[0] = t.x; out[1] = t.y;
+    } else {
+      out[0] = *p;
+    }
+  } else {
+    if constexpr (V == 4) {
+      const uint2 t = *reinterpret_cast<const uint2*>(p);
+      out[0] = __uint_as_float(t.x << 16); out[1] = __uint_as_float(t.x & 0xffff0000u);
+      out[2] = __uint_as_float(t.y << 16); out[3] = __uint_as_float(t.y & 0xffff0000u);
+    } else {
+      static_assert(V == 2, "bf16 rows use V = 2 or 4");
+      const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+      out[0] = __uint_as_float(t << 16); out[1] = __uint_as_float(t & 0xffff0000u);
+    }
+  }
+}
+
+template <int V, bool BF16>
+__device__ __forceinline__ void load_coherent(const typename Elem<BF16>::T* p, float* out) {
+  if constexpr (!BF16) {
+    if constexpr (V == 4) {
+      const uint64_t a = ld_coherent_u64(reinterpret_cast<const uint64_t*>(p));
+      const uint64_t b = ld_coherent_u64(reinterpret_cast<const uint64_t*>(p) + 1);
+      out[0] = __uint_as_float(static_cast<uint32_t>(a));
+      out[1] = __uint_as_float(static_cast<uint32_t>(a >> 32));
+      out[2] = __uint_as_float(static_cast<uint32_t>(b));
+      out[3] = __uint_as_float(static_cast<uint32_t>(b >> 32));
+    } else if constexpr (V == 2) {
+      const uint64_t a = ld_coherent_u64(reinterpret_cast<const uint64_t*>(p));
+      out[0] = __uint_as_float(static_cast<uint32_t>(a));
+      out[1] = __uint_as_float(static_cast<uint32_t>(a >> 32));
+    } else {
+      out[0] = __uint_as_float(ld_coherent_u32(reinterpret_cast<const uint32_t*>(p)));
+    }
+  } else {
+    if constexpr (V == 4) {
+      const uint64_t a = ld_coherent_u64(reinterpret_cast<const uint64_t*>(p));
+      const uint32_t x = static_cast<uint32_t>(a), y = static_cast<uint32_t>(a >> 32);
+      out[0] = __uint_as_float(x << 16); out[1] = __uint_as_float(x & 0xffff0000u);
+      out[2] = __uint_as_float(y << 16); out[3] = __uint_as_float(y & 0xffff0000u);
+    } else {
+      const uint32_t t = ld_coherent_u32(reinterpret_cast<const uint32_t*>(p));
+      out[0] = __uint_as_float(t << 16); out[1] = __uint_as_float(t & 0xffff0000u);
+    }
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void store_coherent_f32(float* p, const float* v) {
+  if constexpr (V == 4) {
+    st_coherent_u64(reinterpret_cast<uint64_t*>(p),
+                    (static_cast<uint64_t>(__float_as_uint(v[1])) << 32) | __float_as_uint(v[0]));
+    st_coherent_u64(reinterpret_cast<uint64_t*>(p) + 1,
+                    (static_cast<uint64_t>(__float_as_uint(v[3])) << 32) | __float_as_uint(v[2]));
+  } else if constexpr (V == 2) {
+    st_coherent_u64(reinterpret_cast<uint64_t*>(p),
+                    (static_cast<uint64_t>(__float_as_uint(v[1])) << 32) | __float_as_uint(v[0]));
+  } else {
+    st_coherent_u32(reinterpret_cast<uint32_t*>(p), __float_as_uint(v[0]));
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void store_coherent_bf16(uint16_t* p, const float* v) {
+  if constexpr (V == 4) {
+    const uint64_t w = static_cast<uint64_t>(f32_to_bf16(v[0])) |
+                       (static_cast<uint64_t>(f32_to_bf16(v[1])) << 16) |
+                       (static_cast<uint64_t>(f32_to_bf16(v[2])) << 32) |
+                       (static_cast<uint64_t>(f32_to_bf16(v[3])) << 48);
+    st_coherent_u64(reinterpret_cast<uint64_t*>(p), w);
+  } else {
+    static_assert(V == 2, "bf16 rows use V = 2 or 4");
+    const uint32_t w = static_cast<uint32_t>(f32_to_bf16(v[0])) |
+                       (static_cast<uint32_t>(f32_to_bf16(v[1])) << 16);
+    st_coherent_u32(reinterpret_cast<uint32_t*>(p), w);
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void load_plain_f32(const float* p, float* out) {
+  load_plain<V, false>(p, out);
+}
+template <int V>
+__device__ __forceinline__ void store_plain_f32(float* p, const float* v) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  } else {
+    *p = v[0];
+  }
+}
+
+// Sum over the G lanes of an aligned lane group; every lane of the group gets
+// the same bits (a butterfly of commutative additions).
+template <int G>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int m = 1; m < G; m <<= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair forces: gradient of the per-vertex loss with respect to z_u.
+// `dotq` is z_u . z_v (sigmoid) or |z_u - z_v|^2 (Student-t), summed over the
+// whole row.  The returned scalar multiplies z_v (sigmoid) or z_u - z_v
+// (Student-t).
+enum Force : int32_t { kSigmoid = 0, kStudentT = 1 };
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// attraction, Eq. 5 (sigmoid: sigma(x) - 1) and Eq. 8 along the unit vector
+// (Student-t: 2 / (1 + q))
+__device__ __forceinline__ float attract_coef(int32_t force, float dotq) {
+  return force == kSigmoid ? -sigmoidf_(-dotq) : 2.0f / (1.0f + dotq);
+}
+// repulsion, Eq. 6 (sigma(x)) and the eps-regularised Eq. 9 along the unit
+// vector (-2 (1 - eps) / ((q + eps)(1 + q)), 0 when q + eps = 0)
+__device__ __forceinline__ float repulse_coef(int32_t force, float dotq, float eps) {
+  if (force == kSigmoid) return sigmoidf_(dotq);
+  const float den = (dotq + eps) * (1.0f + dotq);
+  return den == 0.0f ? 0.0f : -2.0f * (1.0f - eps) / den;
+}
+
+// Loss terms of Eq. 2 (FP32): -log delta for a neighbour, -log(1 - delta) for
+// a negative.  Sigmoid: softplus(-x), softplus(x).  Student-t: log(1 + q) and
+// log((1 + q) / (q + eps)), the latter as log1p((1 - eps) / (q + eps)).
+__device__ __forceinline__ float softplusf_(float y) {
+  return fmaxf(y, 0.0f) + log1pf(expf(-fabsf(y)));
+}
+__device__ __forceinline__ float attract_loss(int32_t force, float dotq) {
+  return force == kSigmoid ? softplusf_(-dotq) : log1pf(dotq);
+}
+__device__ __forceinline__ float repulse_loss(int32_t force, float dotq, float eps) {
+  if (force == kSigmoid) return softplusf_(dotq);
+  return log1pf((1.0f - eps) / (dotq + eps));
+}
+
+}  // namespace f2v

@@ -1,0 +1,16 @@
+// Update and loss kernel instances with V = 2, bf16 rows.
+#include "f2v_update_impl.h"
+
+namespace f2v {
+
+#define F2V_VARIANT(G, V, R, B) \
+  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B>), \
+          reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
+
+extern const Variant kVariants_bf16_v2[] = {
+    F2V_VARIANT(1, 2, 1, true),  F2V_VARIANT(2, 2, 1, true),  F2V_VARIANT(4, 2, 1, true),
+    F2V_VARIANT(8, 2, 1, true),  F2V_VARIANT(16, 2, 1, true), F2V_VARIANT(32, 2, 1, true),
+    F2V_VARIANT(64, 2, 1, true)};
+extern const int kNumVariants_bf16_v2 = sizeof(kVariants_bf16_v2) / sizeof(kVariants_bf16_v2[0]);
+
+}  // namespace f2v

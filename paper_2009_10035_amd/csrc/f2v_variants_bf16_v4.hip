@@ -1,0 +1,16 @@
+// Update and loss kernel instances with V = 4, bf16 rows.
+#include "f2v_update_impl.h"
+
+namespace f2v {
+
+#define F2V_VARIANT(G, V, R, B) \
+  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B>), \
+          reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
+
+extern const Variant kVariants_bf16_v4[] = {
+    F2V_VARIANT(1, 4, 1, true),  F2V_VARIANT(2, 4, 1, true),  F2V_VARIANT(4, 4, 1, true),
+    F2V_VARIANT(8, 4, 1, true),  F2V_VARIANT(16, 4, 1, true), F2V_VARIANT(32, 4, 1, true),
+    F2V_VARIANT(64, 4, 1, true), F2V_VARIANT(64, 4, 2, true), F2V_VARIANT(64, 4, 4, true)};
+extern const int kNumVariants_bf16_v4 = sizeof(kVariants_bf16_v4) / sizeof(kVariants_bf16_v4[0]);
+
+}  // namespace f2v

@@ -1,0 +1,16 @@
+// Update and loss kernel instances with V = 1, FP32 rows.
+#include "f2v_update_impl.h"
+
+namespace f2v {
+
+#define F2V_VARIANT(G, V, R, B) \
+  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B>), \
+          reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
+
+extern const Variant kVariants_f32_v1[] = {
+    F2V_VARIANT(1, 1, 1, false),  F2V_VARIANT(2, 1, 1, false),  F2V_VARIANT(4, 1, 1, false),
+    F2V_VARIANT(8, 1, 1, false),  F2V_VARIANT(16, 1, 1, false), F2V_VARIANT(32, 1, 1, false),
+    F2V_VARIANT(64, 1, 1, false)};
+extern const int kNumVariants_f32_v1 = sizeof(kVariants_f32_v1) / sizeof(kVariants_f32_v1[0]);
+
+}  // namespace f2v

@@ -1,0 +1,60 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and
+compare with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2009_10035_amd as f2v
+
+
+def device_graph(g):
+    rowptr = torch.from_numpy(np.ascontiguousarray(g.rowptr, dtype=np.int64)).cuda()
+    colidx = torch.from_numpy(np.ascontiguousarray(g.colidx, dtype=np.int32)).cuda()
+    return rowptr, colidx
+
+
+def lib_params(g, p: dict, **over):
+    q = dict(p)
+    q.update(over)
+    return f2v.make_params(
+        g.n, g.nnz, q["d"], batch=q["batch"], s=q["s"], force=q["force"],
+        precision=q.get("precision", "fp32"), lr0=q["lr0"], lr_schedule=q.get("lr_schedule", "const"),
+        eps=q.get("eps", 1e-3), total_epochs=q.get("total_epochs", 1),
+        perm_mode=q.get("perm_mode", "random"), schedule=q.get("schedule", "dataflow"),
+        chunk=q.get("chunk", 0), seed=q["seed"])
+
+
+def oracle_params(p: dict, **over) -> oracle.OracleParams:
+    q = dict(p)
+    q.update(over)
+    return oracle.OracleParams(d=q["d"], batch=q["batch"], s=q["s"], force=q["force"],
+                               eps=q.get("eps", 1e-3), lr0=q["lr0"],
+                               lr_schedule=q.get("lr_schedule", "const"),
+                               total_epochs=q.get("total_epochs", 1), seed=q["seed"],
+                               perm_mode=q.get("perm_mode", "random"))
+
+
+def gpu_run(g, Z0, p: dict, epochs: int, first: int = 0, snapshots: bool = True, **over):
+    """Run `epochs` epochs on the device; returns the FP32 states after each
+    epoch (or only the last) as numpy arrays."""
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(Z0, dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p, **over))
+    out = []
+    for e in range(first, first + epochs):
+        tr.epoch(e)
+        if snapshots or e == first + epochs - 1:
+            tr.sync_embedding()
+            out.append(z.cpu().numpy().copy())
+    tr.check()
+    tr.close()
+    return out
+
+
+def rel_fro(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))

@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, the parameter struct matches the header's layout, and host
+validation rejects bad parameters before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2009_10035_amd as f2v
+from paper_2009_10035_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "f2v.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(f2v_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    lib = f2v.load()
+    names = declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_binding.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", f2v._binding.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for name in names:
+        assert re.search(r"\bT " + name + r"\b", out), name
+
+
+def test_params_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "f2v.h"\n'
+                   'int main(void){printf("%zu", sizeof(f2v_params));'
+                   + "".join('printf(" %%zu", offsetof(f2v_params, %s));' % f for f, _ in f2v.Params._fields_)
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(f2v.Params)
+    assert vals[1:] == [getattr(f2v.Params, f).offset for f, _ in f2v.Params._fields_]
+
+
+def good(**over):
+    q = dict(n=1000, nnz=20000, d=128)
+    q.update(over)
+    n, nnz, d = q.pop("n"), q.pop("nnz"), q.pop("d")
+    return f2v.make_params(n, nnz, d, **q)
+
+
+def test_defaults_and_workspace():
+    p = good()
+    assert p.batch == 384 and p.s == 5 and abs(p.lr0 - 0.02) < 1e-9 and p.chunk == 128
+    w128 = f2v.workspace_size(p)
+    w256 = f2v.workspace_size(good(d=256))
+    assert w256 > w128 > 1000 * 128 * 4
+    assert f2v.workspace_size(good(precision="bf16")) < w128 * 2
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n", 0, "F2V_E_INVALID_ARG"), ("n", 2**31, "F2V_E_INVALID_ARG"), ("d", 0, "F2V_E_INVALID_ARG"),
+    ("d", 1025, "F2V_E_INVALID_ARG"), ("d", 130, "F2V_E_UNSUPPORTED"), ("d", 65, "F2V_E_UNSUPPORTED"),
+    ("batch", 0, "F2V_E_INVALID_ARG"), ("s", -1, "F2V_E_INVALID_ARG"), ("s", 65, "F2V_E_INVALID_ARG"),
+    ("force", 2, "F2V_E_INVALID_ARG"), ("precision", 3, "F2V_E_INVALID_ARG"), ("lr0", 0.0, "F2V_E_INVALID_ARG"),
+    ("lr0", float("nan"), "F2V_E_INVALID_ARG"), ("eps", 1.0, "F2V_E_INVALID_ARG"),
+    ("eps", -0.1, "F2V_E_INVALID_ARG"), ("perm_mode", 2, "F2V_E_INVALID_ARG"),
+    ("schedule", 2, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
+])
+def test_validation(field, value, status):
+    p = good()
+    setattr(p, field, value)
+    with pytest.raises(f2v.F2VError) as ei:
+        f2v.workspace_size(p)
+    assert ei.value.name == status
+    assert f2v.load().f2v_last_error(None)
+
+
+def test_linear_schedule_needs_epochs_and_bf16_needs_even_d():
+    p = good(lr_schedule="linear")
+    p.total_epochs = 0
+    with pytest.raises(f2v.F2VError):
+        f2v.workspace_size(p)
+    with pytest.raises(f2v.F2VError) as ei:
+        f2v.workspace_size(good(d=33, precision="bf16"))
+    assert ei.value.name == "F2V_E_UNSUPPORTED"
+    f2v.workspace_size(good(d=33))
+
+
+def test_init_rejects_bad_pointers_without_touching_the_device():
+    lib = f2v.load()
+    p = good()
+    ctx = ctypes.c_void_p()
+    st = lib.f2v_init(ctypes.byref(p), None, None, None, None, 0, None, ctypes.byref(ctx))
+    assert _binding.STATUS[st] == "F2V_E_INVALID_ARG"
+    st = lib.f2v_init(ctypes.byref(p), 256, 512, 1024, 4096, 10, None, ctypes.byref(ctx))
+    assert _binding.STATUS[st] == "F2V_E_OOM"
+    st = lib.f2v_init(ctypes.byref(p), 256, 512, 1024, 4097, 1 << 40, None, ctypes.byref(ctx))
+    assert _binding.STATUS[st] == "F2V_E_INVALID_ARG"   # misaligned workspace
+    assert lib.f2v_epoch(None, 0) == 1 and lib.f2v_destroy(None) == 0
+    assert lib.f2v_status_string(6) == b"device dependency wait timed out"

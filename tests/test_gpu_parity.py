@@ -1,0 +1,187 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance: relative Frobenius error <= 1e-5 per epoch for FP32 (the path
+computes in FP32; one epoch from the same FP32 state is the binding check,
+free-running trajectories are checked on the small workload).  Random streams
+(partition, negatives) must be bit-identical; the two device schedules must be
+bit-identical to each other."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2009_10035_amd as f2v
+from gpu_helpers import device_graph, gpu_run, lib_params, oracle_params, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 65537, 1_000_000])
+def test_partition_bit_identical(n):
+    for seed, epoch in ((0, 0), (2, 7), (2**40 + 5, 1199)):
+        gpu = f2v.partition(n, seed, epoch).cpu().numpy()
+        assert np.array_equal(gpu, oracle.partition(n, seed, epoch)), (n, seed, epoch)
+    assert np.array_equal(f2v.partition(n, 3, 1, mode="identity").cpu().numpy(), np.arange(n))
+
+
+@pytest.mark.parametrize("n,b,s", [(1, 1, 1), (1000, 256, 5), (1_000_000, 384, 5), (4_000_000, 384, 10)])
+def test_negatives_bit_identical(n, b, s):
+    for seed, epoch in ((4, 0), (4, 3), (2**63 + 1, 99)):
+        gpu = f2v.negatives(n, b, s, seed, epoch).cpu().numpy()
+        assert np.array_equal(gpu, oracle.negatives(n, b, s, seed, epoch))
+
+
+@pytest.mark.parametrize("schedule", ["dataflow", "strict"])
+def test_er1k_free_running_20_epochs(schedule):
+    g, p = gg.workload("er1k")
+    Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
+    ref = oracle.run(g, Z0, oracle_params(p), p["total_epochs"])
+    got = gpu_run(g, Z0, p, p["total_epochs"], schedule=schedule)
+    errs = [rel_fro(a, b) for a, b in zip(got, ref)]
+    print("per-epoch relative error", ["%.2e" % e for e in errs])
+    assert max(errs) <= TOL
+
+
+def test_er1k_one_epoch_from_shared_state():
+    g, p = gg.workload("er1k")
+    Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
+    states = oracle.run(g, Z0, oracle_params(p), 12)
+    for e in (0, 5, 11):
+        start = (Z0 if e == 0 else states[e - 1]).astype(np.float32)
+        ref = oracle.epoch(g, start, e, oracle_params(p))
+        got = gpu_run(g, start, p, 1, first=e)[0]
+        err = rel_fro(got, ref)
+        rowmax = np.max(np.abs(got - ref) / (np.abs(ref).max(axis=1, keepdims=True) + 1e-30))
+        assert err <= TOL and rowmax < 1e-3, (e, err, rowmax)
+
+
+@pytest.mark.parametrize("maker,chunk", [
+    (lambda: gg.erdos_renyi(3000, 12.0, 1), 0),
+    (lambda: gg.star(3000), 0),
+    (lambda: gg.star(3000), 64),
+    (lambda: gg.chung_lu(20000, 2.1, 20.0, 3), 0),
+    (lambda: gg.chung_lu(20000, 2.1, 20.0, 3), 16),
+])
+@pytest.mark.parametrize("d,force", [(32, "student_t"), (128, "sigmoid"), (2, "student_t")])
+def test_dataflow_equals_strict_and_oracle(maker, chunk, d, force):
+    g = maker()
+    p = dict(d=d, batch=128, s=5, force=force, lr0=0.02, seed=11, chunk=chunk)
+    Z0 = gg.init_embedding(g.n, d, 3)
+    a = gpu_run(g, Z0, p, 2, schedule="dataflow")
+    b = gpu_run(g, Z0, p, 2, schedule="strict")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    ref = oracle.epoch(g, Z0, 0, oracle_params(p))
+    assert rel_fro(a[0], ref) <= TOL
+
+
+def test_run_twice_and_resume_bitwise():
+    g = gg.chung_lu(30000, 2.1, 20.0, 5)
+    p = dict(d=64, batch=384, s=5, force="sigmoid", lr0=0.02, seed=1)
+    Z0 = gg.init_embedding(g.n, 64, 2)
+    a = gpu_run(g, Z0, p, 6, snapshots=False)[-1]
+    b = gpu_run(g, Z0, p, 6, snapshots=False)[-1]
+    assert np.array_equal(a, b)
+    half = gpu_run(g, Z0, p, 3, snapshots=False)[-1]
+    c = gpu_run(g, half, p, 3, first=3, snapshots=False)[-1]
+    assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 16, 24, 64, 100, 128, 192, 256, 512, 1024])
+@pytest.mark.parametrize("force", ["sigmoid", "student_t"])
+def test_dimensions(d, force):
+    g = gg.erdos_renyi(700, 8.0, d)
+    p = dict(d=d, batch=50, s=4, force=force, lr0=0.05, seed=d, lr_schedule="linear", total_epochs=3)
+    Z0 = gg.init_embedding(g.n, d, d + 1)
+    got = gpu_run(g, Z0, p, 2)
+    ref = oracle.run(g, Z0, oracle_params(p), 2)
+    # conditioning of the trajectory: the oracle's own response to a one-ulp
+    # (FP32) relative perturbation of the start state.  Well-conditioned
+    # cases stay at 1e-5; the 1-D Student-t case amplifies rounding by ~100x
+    # per epoch (near-coincident rows meet the regularised repulsion).
+    rng = np.random.default_rng(0)
+    Zp = Z0.astype(np.float64) * (1 + 2.0**-24 * rng.choice([-1.0, 1.0], size=Z0.shape))
+    pert = oracle.run(g, Zp, oracle_params(p), 2)
+    for x, y, z in zip(got, ref, pert):
+        assert rel_fro(x, y) <= max(TOL, 10 * rel_fro(z, y))
+
+
+@pytest.mark.parametrize("case", ["n1", "isolated", "s0", "b1", "b_ge_n", "identity", "selfloop_dup",
+                                  "eps0", "ragged"])
+def test_edge_cases(case):
+    force = "student_t"
+    if case == "n1":
+        g = gg.CSRGraph(1, np.array([0, 0], np.int64), np.zeros(0, np.int32))
+        p = dict(d=4, batch=3, s=2, force="sigmoid", lr0=0.1, seed=1)
+    elif case == "isolated":
+        g = gg.CSRGraph(6, np.array([0, 1, 2, 2, 2, 2, 2], np.int64), np.array([1, 0], np.int32))
+        p = dict(d=8, batch=4, s=3, force=force, lr0=0.1, seed=2)
+    elif case == "s0":
+        g = gg.erdos_renyi(500, 6.0, 2)
+        p = dict(d=16, batch=64, s=0, force="sigmoid", lr0=0.05, seed=3)
+    elif case == "b1":
+        g = gg.erdos_renyi(200, 6.0, 3)
+        p = dict(d=8, batch=1, s=2, force=force, lr0=0.05, seed=4)
+    elif case == "b_ge_n":
+        g = gg.erdos_renyi(300, 6.0, 4)
+        p = dict(d=32, batch=1000, s=5, force=force, lr0=0.05, seed=5)
+    elif case == "identity":
+        g = gg.path(400)
+        p = dict(d=16, batch=7, s=3, force=force, lr0=0.05, seed=6, perm_mode="identity")
+    elif case == "selfloop_dup":
+        g = gg.CSRGraph(4, np.array([0, 3, 5, 6, 6], np.int64), np.array([0, 1, 1, 0, 2, 1], np.int32))
+        p = dict(d=4, batch=2, s=3, force=force, lr0=0.1, seed=7)
+    elif case == "eps0":
+        g = gg.erdos_renyi(256, 8.0, 5)
+        p = dict(d=32, batch=64, s=5, force=force, lr0=0.01, seed=8, eps=0.0)
+    else:  # ragged: n not a multiple of b, several tiles per row group
+        g = gg.erdos_renyi(1537, 10.0, 6)
+        p = dict(d=128, batch=100, s=5, force="sigmoid", lr0=0.02, seed=9)
+    Z0 = gg.init_embedding(g.n, p["d"], 10)
+    got = gpu_run(g, Z0, p, 3)
+    ref = oracle.run(g, Z0, oracle_params(p), 3)
+    for x, y in zip(got, ref):
+        assert rel_fro(x, y) <= TOL, case
+    got_s = gpu_run(g, Z0, p, 3, schedule="strict")
+    for x, y in zip(got, got_s):
+        assert np.array_equal(x, y), case
+
+
+@pytest.mark.parametrize("force", ["sigmoid", "student_t"])
+def test_loss_parity(force):
+    g = gg.chung_lu(20000, 2.1, 16.0, 8)
+    p = dict(d=32, batch=384, s=5, force=force, lr0=0.02, seed=12)
+    Z0 = gg.init_embedding(g.n, 32, 4)
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(Z0).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p))
+    for e in range(3):
+        got = np.array(tr.loss())
+        tr.sync_embedding()
+        ref = oracle.loss(g, z.cpu().numpy(), oracle_params(p))
+        np.testing.assert_allclose(got, ref, rtol=1e-6)
+        tr.epoch(e)
+    tr.close()
+
+
+def test_csr_validation():
+    g = gg.erdos_renyi(100, 4.0, 1)
+    p = dict(d=8, batch=16, s=2, force="sigmoid", lr0=0.1, seed=1)
+    z = torch.zeros(100, 8, device="cuda")
+    bad_cols = g.colidx.copy()
+    bad_cols[5] = 100
+    for rp, ci, name in ((g.rowptr, bad_cols, "col"), (g.rowptr[::-1].copy(), g.colidx, "rowptr")):
+        rowptr = torch.from_numpy(np.ascontiguousarray(rp)).cuda()
+        colidx = torch.from_numpy(np.ascontiguousarray(ci)).cuda()
+        with pytest.raises(f2v.F2VError) as ei:
+            f2v.Trainer(rowptr, colidx, z, lib_params(g, p))
+        assert ei.value.name == "F2V_E_BAD_GRAPH", name
