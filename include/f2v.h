@@ -72,7 +72,7 @@ typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
 typedef enum { F2V_SCHED_DATAFLOW = 0, F2V_SCHED_STRICT = 1 } f2v_schedule;
 
 typedef struct {
-    int64_t n;            /* vertices, >= 1, < 2^31 */
+    int64_t n;            /* vertices, >= 1, < 2^29 - 1 */
     int64_t nnz;          /* stored CSR entries (2m for a simple undirected graph) */
     int32_t d;            /* embedding dimension: d % 4 == 0 up to 1024, d % 4 == 2
                              up to 128, odd d up to 64 (BF16: even d only) */
@@ -91,14 +91,14 @@ typedef struct {
     int32_t schedule;     /* f2v_schedule */
     int32_t chunk;        /* neighbours per work unit; rows of higher degree are
                              split into several units whose partial sums are
-                             combined in a fixed order.  0 = default (128). */
+                             combined in a fixed order.  0 = default (32). */
     uint64_t seed;        /* key of every random stream */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
- * eps = 1e-3, random partition, dataflow schedule, chunk 128, seed 0.
+ * eps = 1e-3, random partition, dataflow schedule, chunk 32, seed 0.
  * n, nnz and d must still be set. */
 void f2v_default_params(f2v_params *p);
 
@@ -155,6 +155,23 @@ f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int
 /* Device time of the most recent f2v_epoch's update kernel(s) in ms, measured
  * with HIP events on the context's stream (prologue excluded).  Synchronises. */
 f2v_status f2v_last_epoch_ms(f2v_ctx *ctx, float *update_ms, float *total_ms);
+
+/* Diagnostics.  With diagnostics on, each dataflow epoch records 8 counters
+ * per wave of its update kernel (uint64): [0] cycles of the wave, [1] cycles
+ * waiting for rows of earlier batches to be published, [2] cycles combining
+ * split rows, [3] work groups processed, [4] polls that found a row
+ * unpublished, [5] waits that had to poll, [6] cycles storing and publishing
+ * rows, [7] unused.  f2v_wave_stats copies min(cap_waves, waves) rows of the
+ * last such epoch to host memory `out` (may be NULL to query the count) and
+ * synchronises the stream. */
+f2v_status f2v_set_diagnostics(f2v_ctx *ctx, int32_t enable);
+f2v_status f2v_wave_stats(f2v_ctx *ctx, uint64_t *out, int64_t cap_waves, int64_t *n_waves);
+/* Per-vertex timeline of the last epoch run with diagnostics on, in ticks of
+ * the device's constant wall clock (100 MHz on MI355X; low 32 bits): out[2u]
+ * = end of the last dependency wait of the unit that finished vertex u (0 if
+ * it did not wait), out[2u+1] = publication of u's new row.  `out` is host
+ * memory for 2n uint32.  Synchronises. */
+f2v_status f2v_vertex_trace(f2v_ctx *ctx, uint32_t *out);
 
 #ifdef __cplusplus
 }

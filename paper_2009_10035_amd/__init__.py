@@ -85,6 +85,28 @@ class Trainer:
         check(self.lib.f2v_last_epoch_ms(self.ctx, ctypes.byref(u), ctypes.byref(t)), self.ctx)
         return float(u.value), float(t.value)
 
+    def set_diagnostics(self, enable: bool = True) -> None:
+        check(self.lib.f2v_set_diagnostics(self.ctx, 1 if enable else 0), self.ctx)
+
+    def wave_stats(self):
+        """Per-wave counters of the last dataflow epoch run with diagnostics on
+        (numpy uint64 [waves, 8]; see f2v_wave_stats in include/f2v.h)."""
+        import numpy as np
+        n = ctypes.c_int64(0)
+        check(self.lib.f2v_wave_stats(self.ctx, None, 0, ctypes.byref(n)), self.ctx)
+        out = np.zeros((n.value, 8), dtype=np.uint64)
+        check(self.lib.f2v_wave_stats(self.ctx, out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                      ctypes.byref(n)), self.ctx)
+        return out
+
+    def vertex_trace(self):
+        """(wait_end, publish) wall-clock ticks per vertex of the last epoch run
+        with diagnostics on (numpy uint32 [n, 2])."""
+        import numpy as np
+        out = np.zeros((self.params.n, 2), dtype=np.uint32)
+        check(self.lib.f2v_vertex_trace(self.ctx, out.ctypes.data_as(ctypes.c_void_p)), self.ctx)
+        return out
+
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.f2v_destroy(self.ctx)

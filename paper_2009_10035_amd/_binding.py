@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libf2v.so")
 EXPORTS = (
     "f2v_default_params", "f2v_workspace_size", "f2v_init", "f2v_epoch", "f2v_loss",
     "f2v_sync_embedding", "f2v_check", "f2v_destroy", "f2v_status_string", "f2v_last_error",
-    "f2v_partition", "f2v_negatives", "f2v_last_epoch_ms",
+    "f2v_partition", "f2v_negatives", "f2v_last_epoch_ms", "f2v_set_diagnostics", "f2v_wave_stats",
+    "f2v_vertex_trace",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",
@@ -86,6 +87,12 @@ def load(build_if_missing: bool = True):
     L.f2v_negatives.restype = st
     L.f2v_last_epoch_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.f2v_last_epoch_ms.restype = st
+    L.f2v_set_diagnostics.argtypes = [P, ctypes.c_int32]
+    L.f2v_set_diagnostics.restype = st
+    L.f2v_wave_stats.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.f2v_wave_stats.restype = st
+    L.f2v_vertex_trace.argtypes = [P, P]
+    L.f2v_vertex_trace.restype = st
     _lib = L
     return L
 

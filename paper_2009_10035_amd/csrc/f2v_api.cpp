@@ -19,17 +19,18 @@ using f2v::Variant;
 
 namespace {
 
-constexpr int kDefaultChunk = 128;
+constexpr int kDefaultChunk = 32;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
 
 struct Layout {
-  size_t zbuf1, bbuf0, bbuf1, perm, bid, ucnt, uoff, negs, btot, breal, bstart, ngroups, tmap,
-      stamp, hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part,
-      loss_out, total;
+  size_t zbuf1, bbuf0, bbuf1, perm, word, ucnt, uoff, negs, btot, breal, bstart, ngroups, units,
+      hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part, loss_out,
+      wave_stats, trace, total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
 
@@ -42,8 +43,9 @@ Layout layout_of(const f2v_params& p) {
   const int64_t n = p.n, d = p.d;
   const int32_t chunk = chunk_of(p);
   L.nb = (n + p.batch - 1) / p.batch;
-  // a split row of degree deg > chunk has ceil(deg/chunk) < 2 deg / chunk units
-  L.hub_slot_cap = 2 * (p.nnz / chunk) + 1;
+  // a split row of degree deg > chunk has m = ceil(deg/chunk) < 2 deg / chunk
+  // units, and its combining tree at most 1.5 m nodes
+  L.hub_slot_cap = 3 * ((p.nnz + chunk - 1) / chunk) + 8;
   // tickets: one per unit, plus at most 63 padding tickets per batch
   L.tmap_cap = n + p.nnz / chunk + L.nb * 63 + 64;
   size_t off = 0;
@@ -53,7 +55,7 @@ Layout layout_of(const f2v_params& p) {
   L.bbuf0 = take(bf16 ? size_t(n) * d * 2 : 0);
   L.bbuf1 = take(bf16 ? size_t(n) * d * 2 : 0);
   L.perm = take(size_t(n) * 4);
-  L.bid = take(size_t(n) * 4);
+  L.word = take(size_t(n) * 4);
   L.ucnt = take(size_t(n) * 4);
   L.uoff = take(size_t(n) * 4);
   L.negs = take(size_t(L.nb) * (p.s > 0 ? p.s : 1) * 4);
@@ -61,10 +63,9 @@ Layout layout_of(const f2v_params& p) {
   L.breal = take(size_t(L.nb) * 4);
   L.bstart = take(size_t(L.nb + 1) * 4);
   L.ngroups = take(4);
-  L.tmap = take(size_t(L.tmap_cap) * 8);
-  L.stamp = take(size_t(n) * 4);
+  L.units = take(size_t(L.tmap_cap) * sizeof(f2v::Unit));
   L.hub_base = take(size_t(n) * 8);
-  L.hub_cnt = take(size_t(n) * 4);
+  L.hub_cnt = take(size_t(L.hub_slot_cap) * 4);
   L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
   L.err = take(4);
   L.csr_flag = take(4);
@@ -72,6 +73,8 @@ Layout layout_of(const f2v_params& p) {
   L.scan_total = take(8);
   L.loss_part = take(size_t(n) * 16);
   L.loss_out = take(3 * 8);
+  L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
+  L.trace = take(size_t(n) * 8);
   L.total = off;
   return L;
 }
@@ -84,8 +87,8 @@ f2v_status fail(std::string* where, f2v_status st, const std::string& msg) {
 
 f2v_status validate(const f2v_params* p, std::string* msg) {
   if (!p) return fail(msg, F2V_E_INVALID_ARG, "params is NULL");
-  if (p->n < 1 || p->n >= (int64_t{1} << 31) - 1)
-    return fail(msg, F2V_E_INVALID_ARG, "n must be in [1, 2^31 - 1)");
+  if (p->n < 1 || p->n >= (int64_t{1} << 29) - 1)
+    return fail(msg, F2V_E_INVALID_ARG, "n must be in [1, 2^29 - 1)");
   if (p->nnz < 0 || p->nnz >= (int64_t{1} << 40)) return fail(msg, F2V_E_INVALID_ARG, "nnz out of range");
   if (p->d < 1 || p->d > 1024) return fail(msg, F2V_E_INVALID_ARG, "d must be in [1, 1024]");
   if (p->precision != F2V_FP32 && p->precision != F2V_BF16)
@@ -128,10 +131,12 @@ struct f2v_ctx {
   float* zbuf[2] = {nullptr, nullptr};
   uint16_t* bbuf[2] = {nullptr, nullptr};
   int cur = 0;
-  uint32_t gen = 0;
   const Variant* var = nullptr;
   int update_grid = 0;
   int cus = 0;
+  bool cooperative = true;  // launch the dataflow kernel with the co-residency guarantee
+  bool diagnostics = false; // collect per-wave counters in dataflow epochs
+  int64_t stat_waves = 0;   // waves of the last epoch with counters
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   bool timed = false;
   std::string err;
@@ -257,6 +262,10 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   }
   if (per_cu < 1) per_cu = 1;
   c->update_grid = per_cu * c->cus;
+  // F2V_COOPERATIVE=0 launches the same grid without the cooperative API (some
+  // profilers do not support cooperative launches); the grid is still sized to
+  // the occupancy limit, and a wait that cannot complete ends at its bound.
+  if (const char* env = std::getenv("F2V_COOPERATIVE")) c->cooperative = std::atoi(env) != 0;
   for (hipEvent_t& e : c->ev)
     if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
 
@@ -282,8 +291,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   int64_t hub_total = 0;
   if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
-      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.stamp), 0u, p->n, s)) != hipSuccess ||
-      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, p->n, s)) != hipSuccess)
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, L.hub_slot_cap, s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
   if (bf16 && (he = f2v::launch_to_bf16(d_z, c->bbuf[0], p->n * int64_t(p->d), s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("bf16 copy: ") + hipGetErrorString(he));
@@ -303,23 +311,19 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   const hipStream_t s = c->stream;
   const bool bf16 = p.precision == F2V_BF16;
   const int slots = slots_of(c->var);
-  if (++c->gen == 0) {  // generations never repeat: restart the stamps after a wrap
-    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(L.stamp), 0u, p.n, s));
-    c->gen = 1;
-  }
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
 
   SetupArgs sa{};
   sa.rowptr = c->rowptr;
   sa.perm = c->at<int32_t>(L.perm);
-  sa.bid = c->at<int32_t>(L.bid);
+  sa.word = c->at<uint32_t>(L.word);
   sa.ucnt = c->at<int32_t>(L.ucnt);
   sa.uoff = c->at<int32_t>(L.uoff);
   sa.negs = c->at<int32_t>(L.negs);
   sa.btot = c->at<int32_t>(L.btot);
   sa.breal = c->at<int32_t>(L.breal);
   sa.bstart = c->at<int32_t>(L.bstart);
-  sa.tmap = c->at<int2>(L.tmap);
+  sa.units = c->at<f2v::Unit>(L.units);
   sa.ngroups = c->at<int32_t>(L.ngroups);
   sa.n = p.n;
   sa.b = p.batch;
@@ -336,7 +340,6 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   HIP_TRY(c, f2v::launch_setup(sa, s));
 
   EpochArgs A{};
-  A.rowptr = c->rowptr;
   A.colidx = c->colidx;
   if (bf16) {
     A.zc = c->bbuf[c->cur];
@@ -347,14 +350,11 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
     A.zn = c->zbuf[1 - c->cur];
     A.master = nullptr;
   }
-  A.perm = sa.perm;
-  A.bid = sa.bid;
-  A.ucnt = sa.ucnt;
+  A.word = sa.word;
   A.negs = sa.negs;
-  A.tmap = sa.tmap;
+  A.units = sa.units;
   A.bstart = sa.bstart;
   A.ngroups = sa.ngroups;
-  A.stamp = c->at<uint32_t>(L.stamp);
   A.hub_base = c->at<int64_t>(L.hub_base);
   A.hub_cnt = c->at<uint32_t>(L.hub_cnt);
   A.hub_part = c->at<float>(L.hub_part);
@@ -364,17 +364,24 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.b = p.batch;
   A.s = p.s;
   A.nb = static_cast<int32_t>(L.nb);
-  A.chunk = p.chunk;
   A.force = p.force;
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
-  A.gen = c->gen;
   A.spin_limit = kSpinLimit;
+  A.wave_stats = nullptr;
+  A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
+  if (c->diagnostics && p.schedule == F2V_SCHED_DATAFLOW && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {
+    A.wave_stats = c->at<uint64_t>(L.wave_stats);
+    c->stat_waves = int64_t(c->update_grid) * (kBlock / 64);
+  }
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (p.schedule == F2V_SCHED_DATAFLOW) {
     A.strict_batch = -1;
     void* args[] = {&A};
-    HIP_TRY(c, hipLaunchCooperativeKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+    if (c->cooperative)
+      HIP_TRY(c, hipLaunchCooperativeKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+    else
+      HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
   } else {
     const int64_t groups_hint = (p.batch + slots - 1) / slots;
     int grid = static_cast<int>((groups_hint + 3) / 4);
@@ -401,6 +408,34 @@ f2v_status f2v_last_epoch_ms(f2v_ctx* c, float* update_ms, float* total_ms) {
   HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[2]));
   if (update_ms) *update_ms = u;
   if (total_ms) *total_ms = t;
+  return F2V_OK;
+}
+
+f2v_status f2v_set_diagnostics(f2v_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  c->diagnostics = enable != 0;
+  return F2V_OK;
+}
+
+f2v_status f2v_wave_stats(f2v_ctx* c, uint64_t* out, int64_t cap_waves, int64_t* n_waves) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (!n_waves) return fail(&c->err, F2V_E_INVALID_ARG, "n_waves is NULL");
+  if (c->stat_waves == 0) return fail(&c->err, F2V_E_STATE, "no dataflow epoch ran with diagnostics on");
+  *n_waves = c->stat_waves;
+  if (!out) return F2V_OK;
+  const int64_t w = cap_waves < c->stat_waves ? cap_waves : c->stat_waves;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(out, c->at<uint64_t>(c->L.wave_stats), size_t(w) * f2v::kWaveStats * 8,
+                       hipMemcpyDeviceToHost));
+  return F2V_OK;
+}
+
+f2v_status f2v_vertex_trace(f2v_ctx* c, uint32_t* out) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(&c->err, F2V_E_INVALID_ARG, "out is NULL");
+  if (c->stat_waves == 0) return fail(&c->err, F2V_E_STATE, "no epoch ran with diagnostics on");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(out, c->at<uint32_t>(c->L.trace), size_t(c->p.n) * 8, hipMemcpyDeviceToHost));
   return F2V_OK;
 }
 

@@ -222,11 +222,31 @@ __device__ __forceinline__ void store_plain_f32(float* p, const float* v) {
 }
 
 // Sum over the G lanes of an aligned lane group; every lane of the group gets
-// the same bits (a butterfly of commutative additions).
+// the same bits.  Inside a row of 16 lanes: DPP exchanges (xor 1, xor 2, then
+// the half-row and row mirrors, each a commutative addition, so all lanes
+// agree); across rows: the row sums read into scalars and added once.
+// Must be called with all 64 lanes active.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_swap_add(float x) {
+  return x + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), kCtrl,
+                                                                 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float x, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+}
 template <int G>
 __device__ __forceinline__ float group_sum(float x) {
-#pragma unroll
-  for (int m = 1; m < G; m <<= 1) x += __shfl_xor(x, m, 64);
+  if constexpr (G >= 2) x = dpp_swap_add<0xB1>(x);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) x = dpp_swap_add<0x4E>(x);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) x = dpp_swap_add<0x141>(x);  // row_half_mirror
+  if constexpr (G >= 16) x = dpp_swap_add<0x140>(x); // row_mirror
+  if constexpr (G == 32) {
+    const float s0 = lane_value(x, 0) + lane_value(x, 16);
+    const float s1 = lane_value(x, 32) + lane_value(x, 48);
+    x = (threadIdx.x & 32) ? s1 : s0;
+  } else if constexpr (G == 64) {
+    x = (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+  }
   return x;
 }
 

@@ -6,45 +6,60 @@
 
 namespace f2v {
 
+// Per-vertex word of an epoch: the vertex's batch index, with the top bit set
+// once the batch that updates it has published its new row.
+constexpr uint32_t kPublished = 0x80000000u;
+
+// One work unit of an epoch: chunk c (of nch) of vertex u's neighbour list,
+// len entries from CSR offset beg; u < 0 marks a padding ticket.
+struct alignas(16) Unit {
+  int64_t beg;
+  int32_t u, k, c, nch, len, pad;
+};
+
+// Per-wave counters of the update kernel (diagnostics): kernel cycles, cycles
+// spent waiting for publications, cycles in split-row combines, work groups
+// processed, polls that found a row unpublished, waits that had to poll.
+enum WaveStat { kStatCycles = 0, kStatWaitCycles, kStatCombineCycles, kStatGroups, kStatPolls,
+                kStatWaits, kStatPublishCycles, kWaveStats = 8 };
+
 // Everything one epoch's update kernel reads or writes.
 struct EpochArgs {
-  const int64_t* rowptr;    // [n+1]
   const int32_t* colidx;    // [nnz]
   const void* zc;           // rows read this epoch: float or bf16 [n][d]
   void* zn;                 // rows written this epoch (same type) [n][d]
   float* master;            // BF16 form: FP32 master rows, updated in place
-  const int32_t* perm;      // position -> vertex
-  const int32_t* bid;       // vertex -> batch index of this epoch
-  const int32_t* ucnt;      // position -> work units of that row
+  uint32_t* word;           // vertex -> batch index | kPublished
   const int32_t* negs;      // [nb][s] shared negatives of each batch
-  const int2* tmap;         // ticket -> (position, chunk); position < 0 marks padding
+  const Unit* units;        // ticket -> work unit, in batch order
   const int32_t* bstart;    // [nb+1] first ticket of each batch (multiple of the slot count)
   const int32_t* ngroups;   // device scalar: ticket groups this epoch
-  uint32_t* stamp;          // vertex -> generation whose next row is published
-  const int64_t* hub_base;  // vertex -> first partial-gradient slot (split rows)
-  uint32_t* hub_cnt;        // vertex -> arrival counter of its units
-  float* hub_part;          // [slots][d] partial attraction sums of split rows
+  const int64_t* hub_base;  // vertex -> first node of its combining tree (split rows)
+  uint32_t* hub_cnt;        // tree node -> arrival counter (accumulates over epochs)
+  float* hub_part;          // tree node -> partial sum [d]
   uint32_t* err;            // device error word (bit 0: a wait exceeded its bound)
+  uint64_t* wave_stats;     // optional [waves][kWaveStats] cycle counters (nullptr: off)
+  uint32_t* trace;          // optional [n][2] wall-clock ticks: end of the last wait of the
+                            // row's final unit, and its publication (nullptr: off)
   int64_t n;
-  int32_t d, b, s, nb, chunk, force;
+  int32_t d, b, s, nb, force;
   float lr, eps;
-  uint32_t gen;             // generation stamped by this launch (never repeats)
   int32_t strict_batch;     // >= 0: process only this batch, no waits
   uint32_t spin_limit;      // bound on polls of one dependency wait
 };
 
-// Prologue of an epoch (random partition, negatives, ticket map).
+// Prologue of an epoch (random partition, negatives, work units).
 struct SetupArgs {
   const int64_t* rowptr;
-  int32_t* perm;
-  int32_t* bid;
-  int32_t* ucnt;
+  int32_t* perm;            // position -> vertex
+  uint32_t* word;           // vertex -> batch index (unpublished)
+  int32_t* ucnt;            // position -> work units of that row
   int32_t* uoff;            // position -> unit offset inside its batch
   int32_t* negs;
-  int32_t* btot;            // [nb] padded unit count of each batch, then its first ticket
+  int32_t* btot;            // [nb] unit count of each batch padded to the slot count
   int32_t* breal;           // [nb] unit count of each batch
   int32_t* bstart;          // [nb+1]
-  int2* tmap;
+  Unit* units;
   int32_t* ngroups;
   int64_t n;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave

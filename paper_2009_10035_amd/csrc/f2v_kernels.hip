@@ -31,8 +31,8 @@ __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
   return deg <= chunk ? 1 : static_cast<int32_t>((deg + chunk - 1) / chunk);
 }
 
-// K1: partition (position -> vertex, vertex -> batch), units per position,
-// and the shared negatives of every batch.
+// K1: partition (position -> vertex, vertex -> batch word), units per
+// position, and the shared negatives of every batch.
 __global__ void k_setup_positions(SetupArgs A) {
   const Feistel f{A.seed, A.epoch, A.feistel_half, A.feistel_mask, A.n};
   const int64_t nneg = static_cast<int64_t>(A.nb) * A.s;
@@ -42,7 +42,7 @@ __global__ void k_setup_positions(SetupArgs A) {
     if (i < A.n) {
       const int32_t v = A.identity ? static_cast<int32_t>(i) : feistel_permute(f, i);
       A.perm[i] = v;
-      A.bid[v] = static_cast<int32_t>(i / A.b);
+      A.word[v] = static_cast<uint32_t>(i / A.b);
       A.ucnt[i] = units_of(A.rowptr[v + 1] - A.rowptr[v], A.chunk);
     }
     if (i < nneg) {
@@ -100,8 +100,9 @@ __global__ void k_batch_starts(SetupArgs A) {
   }
 }
 
-// K4: ticket map.  Threads [0, n) place the units of one position; threads
-// [n, n + nb*slots) mark the padding tickets at the end of each batch.
+// K4: work units in ticket order.  Threads [0, n) write the units of one
+// position; threads [n, n + nb*slots) mark the padding tickets at the end of
+// each batch.
 __global__ void k_tickets(SetupArgs A) {
   const int64_t pad_threads = static_cast<int64_t>(A.nb) * A.slots;
   const int64_t total = A.n + pad_threads;
@@ -110,14 +111,31 @@ __global__ void k_tickets(SetupArgs A) {
     if (i < A.n) {
       const int32_t k = static_cast<int32_t>(i / A.b);
       const int64_t t0 = static_cast<int64_t>(A.bstart[k]) + A.uoff[i];
+      const int32_t u = A.perm[i];
       const int32_t cnt = A.ucnt[i];
-      for (int32_t c = 0; c < cnt; ++c) A.tmap[t0 + c] = make_int2(static_cast<int32_t>(i), c);
+      const int64_t r0 = A.rowptr[u], deg = A.rowptr[u + 1] - r0;
+      for (int32_t c = 0; c < cnt; ++c) {
+        Unit w;
+        w.beg = r0 + static_cast<int64_t>(c) * A.chunk;
+        w.u = u;
+        w.k = k;
+        w.c = c;
+        w.nch = cnt;
+        const int64_t rest = deg - static_cast<int64_t>(c) * A.chunk;
+        w.len = static_cast<int32_t>(rest < A.chunk ? rest : A.chunk);
+        w.pad = 0;
+        A.units[t0 + c] = w;
+      }
     } else {
       const int64_t j = i - A.n;
       const int32_t k = static_cast<int32_t>(j / A.slots);
       const int32_t q = static_cast<int32_t>(j % A.slots);
       const int64_t t = static_cast<int64_t>(A.bstart[k]) + A.breal[k] + q;
-      if (t < A.bstart[k + 1]) A.tmap[t] = make_int2(-1, 0);
+      if (t < A.bstart[k + 1]) {
+        Unit w{};
+        w.u = -1;
+        A.units[t] = w;
+      }
     }
   }
 }
@@ -146,12 +164,24 @@ __global__ void k_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_
   }
 }
 
-// Split-row partial slots: count per vertex (its unit count if split, else 0).
+// Nodes of the combining tree of a split row with `units` units: the units,
+// then ceil(count / 8) nodes per level up to a single root.
+__device__ __forceinline__ int64_t tree_nodes(int64_t units) {
+  int64_t total = units, count = units;
+  while (count > 1) {
+    count = (count + 7) / 8;
+    total += count;
+  }
+  return total;
+}
+
+// Split-row slots (partial sums and arrival counters): per vertex, the nodes
+// of its combining tree if split, else 0.
 __global__ void k_hub_counts(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t deg = rowptr[i + 1] - rowptr[i];
-    out[i] = deg > chunk ? units_of(deg, chunk) : 0;
+    out[i] = deg > chunk ? tree_nodes(units_of(deg, chunk)) : 0;
   }
 }
 

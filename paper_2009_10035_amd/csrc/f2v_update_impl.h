@@ -3,30 +3,39 @@
 //
 // Work decomposition.  A lane group of G lanes owns one vertex row u (each lane
 // holds R vectors of V consecutive elements), so a wave processes 64/G rows at
-// once.  Rows of degree above `chunk` are split into several work units of at
-// most `chunk` neighbours; each unit stores its partial attraction sum and the
-// last unit to arrive adds all partials in unit order, then the repulsion and
-// the step, so the result does not depend on which unit finishes last.
+// once.  A work unit is one row's neighbour list, or for rows of degree above
+// `chunk` one chunk of it; the first unit of a row also carries the batch's
+// shared negatives.  Units of a split row store partial sums and the last one
+// to arrive adds all partials in unit order, then takes the step, so the result
+// does not depend on which unit finishes last.
 //
 // Synchronous minibatch semantics on a device that overlaps batches.  The
 // epoch reads rows from `zc` (the state at the start of the epoch) and writes
 // every updated row once into `zn`.  A unit of batch k reading vertex x takes
-// zn[x] if x belongs to an earlier batch (after waiting until x's stamp shows
-// this launch's generation) and zc[x] otherwise, so every read sees exactly the
-// state the sequential algorithm has at the start of batch k.  Units are
-// visited in batch order (the ticket map), a wave's lane groups always belong
-// to one batch and waits are only on earlier batches, so a co-resident grid
-// always makes progress.
+// zn[x] if x belongs to an earlier batch (after waiting until x's word shows it
+// published) and zc[x] otherwise, so every read sees exactly the state the
+// sequential algorithm has at the start of batch k.  Units are visited in
+// batch order, a wave's lane groups always belong to one batch and waits are
+// only on earlier batches, so a co-resident grid always makes progress.
 #pragma once
 #include "f2v_device.h"
 #include "f2v_kernels.h"
 
 namespace f2v {
 
+// List entries fetched per step: kIdxPerLane per lane, kStep per lane group
+// (64 for G >= 4, so a default-size unit and its negatives take one step).
 template <int G>
 struct ListShape {
-  static constexpr int kIdxPerLane = G >= 16 ? 1 : 16 / G;  // indices each lane fetches per step
-  static constexpr int kStep = G * kIdxPerLane;              // list entries per step
+  static constexpr int kIdxPerLane = (64 / G) < 16 ? (64 / G) : 16;
+  static constexpr int kStep = G * kIdxPerLane;
+};
+
+// Loss kernel: neighbours fetched per step.
+template <int G>
+struct LossShape {
+  static constexpr int kIdxPerLane = G >= 16 ? 1 : 16 / G;
+  static constexpr int kStep = G * kIdxPerLane;
 };
 
 template <int G, int R>
@@ -35,27 +44,31 @@ struct Unroll {
   static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : 8);
 };
 
-// Wait until every listed vertex that an earlier batch updates has been
-// published by this launch.  Bounded: after spin_limit polls (or once another
-// wave has reported a timeout) it sets the error word and returns.
-template <int K>
-__device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&idx)[K],
-                                               const bool (&from_next)[K]) {
-  bool pending[K];
+// Diagnostic counters of one wave (kept in registers, written at kernel end).
+struct WaveCounters {
+  uint64_t wait = 0, combine = 0, publish = 0, groups = 0, polls = 0, waits = 0;
+  uint64_t last_wait_end = 0;  // wall clock at the end of the unit's last wait
+};
+
+// Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
+// Bounded: after spin_limit polls (or once another wave has reported a
+// timeout) it sets the error word and returns.  Polls back off from 64 to 512
+// cycles of sleep.
+template <int U>
+__device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
+                                               bool (&pend)[U], WaveCounters& wc) {
   bool any = false;
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    pending[i] = idx[i] >= 0 && from_next[i];
-    any |= pending[i];
-  }
+  for (int q = 0; q < U; ++q) any |= pend[q];
   if (!__any(any)) return;
+  const uint64_t t0 = A.wave_stats ? clock64() : 0;
   uint32_t polls = 0;
   while (true) {
     any = false;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if (pending[i]) pending[i] = ld_coherent_u32(A.stamp + idx[i]) != A.gen;
-      any |= pending[i];
+    for (int q = 0; q < U; ++q) {
+      if (pend[q]) pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+      any |= pend[q];
     }
     if (!__any(any)) break;
     ++polls;
@@ -64,9 +77,17 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
       break;
     }
     if ((polls & 255u) == 0 && ld_coherent_u32(A.err) != 0) break;
-    __builtin_amdgcn_s_sleep(1);
+    if (polls < 16) __builtin_amdgcn_s_sleep(1);
+    else if (polls < 64) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(8);
   }
   compiler_fence();
+  if (A.wave_stats) {
+    wc.wait += clock64() - t0;
+    wc.polls += polls;
+    wc.waits += 1;
+  }
+  if (A.trace) wc.last_wait_end = wall_clock64();
 }
 
 // Row elements owned by lane l of a group: R vectors of V at (r*G + l)*V.
@@ -109,90 +130,159 @@ __device__ __forceinline__ float pair_partial(int32_t force, const float (&a)[R]
   return s;
 }
 
-// Accumulate the forces between the group's row `a` and the rows of `list`
-// (len entries): attraction for CSR neighbours, repulsion for the batch's
-// negatives.  Entries are added in list order.
+// Entry of a step's reordered list (LDS): vertex id in the low bits, then
+// flags: repulsive (a negative), pending (published row not yet seen), and
+// from-next (a vertex of an earlier batch, read from the next buffer).
+constexpr uint32_t kEntVertex = (1u << 29) - 1u;
+constexpr uint32_t kEntRepulsive = 1u << 29;
+constexpr uint32_t kEntPending = 1u << 30;
+constexpr uint32_t kEntNext = 1u << 31;
+constexpr uint32_t kEntNone = kEntVertex;  // no entry (vertex ids stay below it)
+
+// Fan-in of the combining tree of split rows.
+constexpr int kFanIn = 8;
+
+// Forces between the group's row `a` and the entries of its unit's list:
+// `len` CSR neighbours from `nbr` (attraction), then `nneg` shared negatives
+// from `neg` (repulsion).  The list is taken in steps; inside a step the
+// entries read from the epoch-start buffer are accumulated first and those of
+// earlier batches (which may need a wait) after them, each part in list order.
+// The order depends only on the list and the partition, never on timing.
 template <int G, int V, int R, bool BF16>
-__device__ __forceinline__ void accumulate_list(const EpochArgs& A, bool active, bool repulsive,
-                                                const int32_t* list, int64_t len, int32_t k,
-                                                bool wait, int l, int slot,
-                                                const float (&a)[R][V], float (&acc)[R][V]) {
+__device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active, const int32_t* nbr,
+                                                int32_t len, const int32_t* neg, int32_t nneg,
+                                                int32_t k, bool wait, int l, int slot,
+                                                uint32_t* order, const float (&a)[R][V],
+                                                float (&acc)[R][V], WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
   constexpr int K = ListShape<G>::kIdxPerLane;
   constexpr int kStep = ListShape<G>::kStep;
   constexpr int U = Unroll<G, R>::value < kStep ? Unroll<G, R>::value : kStep;
   const T* zc = static_cast<const T*>(A.zc);
   const T* zn = static_cast<const T*>(A.zn);
-  const int holder0 = slot * G;
-  for (int64_t off = 0;; off += kStep) {
-    const bool more = active && off < len;
+  const int lane = slot * G + l;
+  const uint64_t group_mask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (slot * G));
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t* my_order = order + slot * kStep;
+  const int32_t total = active ? len + nneg : 0;
+  for (int32_t off = 0;; off += kStep) {
+    const bool more = off < total;
     if (!__any(more)) break;
-    int32_t idx[K];
-    bool nxt[K];
+    // entries e = off + l + i*G of this step, their source buffer and state
+    uint32_t ent[K];
+    bool cur[K], nxt[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const int64_t e = off + l + i * G;
-      idx[i] = (more && e < len) ? list[e] : -1;
-    }
-#pragma unroll
-    for (int i = 0; i < K; ++i) nxt[i] = idx[i] >= 0 && A.bid[idx[i]] < k;
-    if (wait) wait_published<K>(A, idx, nxt);
-#pragma unroll
-    for (int jb = 0; jb < kStep; jb += U) {
-      float y[U][R][V];
-      int32_t vid[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int j = jb + q;
-        vid[q] = __shfl(idx[j / G], holder0 + (j % G), 64);
-        const int vn = __shfl(static_cast<int>(nxt[j / G]), holder0 + (j % G), 64);
-        if (vid[q] >= 0) {
-          load_row<G, V, R, BF16>(vn ? zn : zc, vid[q], A.d, l, vn != 0, y[q]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
-        }
+      const int32_t e = off + l + i * G;
+      const bool valid = more && e < total;
+      const int32_t v = !valid ? -1 : (e < len ? nbr[e] : neg[e - len]);
+      ent[i] = kEntNone;
+      cur[i] = nxt[i] = false;
+      if (valid) {
+        const uint32_t wd = ld_coherent_u32(A.word + v);
+        const bool from_next = static_cast<int32_t>(wd & ~kPublished) < k;
+        ent[i] = static_cast<uint32_t>(v) | (e >= len ? kEntRepulsive : 0u) |
+                 (from_next ? kEntNext : 0u) |
+                 ((wait && from_next && (wd & kPublished) == 0u) ? kEntPending : 0u);
+        cur[i] = !from_next;
+        nxt[i] = from_next;
       }
+    }
+    // positions in the reordered step: epoch-start rows, then earlier-batch
+    // rows, then empty slots, each in list order
+    uint64_t bc[K], bn[K];
+    int ncur = 0, nnext = 0;
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const float dq = group_sum<G>(pair_partial<R, V>(A.force, a, y[q]));
-        if (vid[q] >= 0) {
-          const float c = repulsive ? repulse_coef(A.force, dq, A.eps) : attract_coef(A.force, dq);
-          if (A.force == kSigmoid) {
+    for (int i = 0; i < K; ++i) {
+      bc[i] = __ballot(cur[i]) & group_mask;
+      bn[i] = __ballot(nxt[i]) & group_mask;
+      ncur += __popcll(bc[i]);
+      nnext += __popcll(bn[i]);
+    }
+    int before_c = 0, before_n = 0, before_x = 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+    for (int i = 0; i < K; ++i) {
+      const uint64_t bx = group_mask & ~bc[i] & ~bn[i];
+      int pos;
+      if (cur[i]) pos = before_c + __popcll(bc[i] & below);
+      else if (nxt[i]) pos = ncur + before_n + __popcll(bn[i] & below);
+      else pos = ncur + nnext + before_x + __popcll(bx & below);
+      my_order[pos] = ent[i];
+      before_c += __popcll(bc[i]);
+      before_n += __popcll(bn[i]);
+      before_x += __popcll(bx);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // region 0: rows of the epoch-start buffer (no wait); region 1: rows of
+    // earlier batches, each awaited just before it is loaded
+    for (int region = 0; region < 2; ++region) {
+      const int rbeg = region == 0 ? 0 : ncur;
+      const int rlen = region == 0 ? ncur : nnext;
+      for (int jb = 0; __any(jb < rlen); jb += U) {
+        int32_t vid[U];
+        bool pend[U], vn[U], rep[U];
 #pragma unroll
-              for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, y[q][r][i], acc[r][i]);
+        for (int q = 0; q < U; ++q) {
+          const uint32_t e = jb + q < rlen ? my_order[rbeg + jb + q] : kEntNone;
+          vid[q] = (e & kEntVertex) == kEntNone ? -1 : static_cast<int32_t>(e & kEntVertex);
+          pend[q] = vid[q] >= 0 && (e & kEntPending) != 0u;
+          vn[q] = (e & kEntNext) != 0u;
+          rep[q] = (e & kEntRepulsive) != 0u;
+        }
+        if (wait && region == 1) wait_published<U>(A, vid, pend, wc);
+        float y[U][R][V];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (vid[q] >= 0) {
+            load_row<G, V, R, BF16>(vn[q] ? zn : zc, vid[q], A.d, l, vn[q], y[q]);
           } else {
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-              for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, a[r][i] - y[q][r][i], acc[r][i]);
+              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+          }
+        }
+        float dq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
+#pragma unroll
+        for (int q = 0; q < U; ++q) dq[q] = group_sum<G>(dq[q]);
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (vid[q] >= 0) {
+            const float c = rep[q] ? repulse_coef(A.force, dq[q], A.eps) : attract_coef(A.force, dq[q]);
+            if (A.force == kSigmoid) {
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, y[q][r][i], acc[r][i]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, a[r][i] - y[q][r][i], acc[r][i]);
+            }
           }
         }
       }
     }
+    // the next step overwrites the order: every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
-// One work unit: position p of the epoch's order, chunk c of its row.
+// One work unit (chunk w.c of vertex w.u's list in batch w.k).
 template <int G, int V, int R, bool BF16>
-__device__ __forceinline__ void process_unit(const EpochArgs& A, int32_t p, int32_t c, int l,
-                                             int slot, bool wait) {
+__device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
+                                             bool wait, uint32_t* order, WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
-  const bool active = p >= 0;
-  int32_t u = 0, k = 0, nch = 1;
-  int64_t beg = 0, len = 0;
-  if (active) {
-    u = A.perm[p];
-    k = p / A.b;
-    nch = A.ucnt[p];
-    const int64_t r0 = A.rowptr[u], r1 = A.rowptr[u + 1];
-    beg = r0 + static_cast<int64_t>(c) * A.chunk;
-    len = r1 - beg < A.chunk ? r1 - beg : A.chunk;
-  }
+  const bool active = w.u >= 0;
+  const int32_t u = active ? w.u : 0;
+  wc.last_wait_end = 0;
   float a[R][V], acc[R][V];
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -207,15 +297,27 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, int32_t p, int3
       for (int i = 0; i < V; ++i) a[r][i] = 0.0f;
   }
 
-  // attraction over this unit's neighbours (Algorithm 2, first inner loop)
-  accumulate_list<G, V, R, BF16>(A, active, false, A.colidx + beg, len, k, wait, l, slot, a, acc);
+  // attraction over the unit's neighbours, then (first unit of the row)
+  // repulsion from the batch's shared negatives: Algorithm 2's two loops
+  const int32_t nneg = (active && w.c == 0) ? A.s : 0;
+  accumulate_unit<G, V, R, BF16>(A, active, A.colidx + w.beg, w.len,
+                                 A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s, nneg,
+                                 w.k, wait, l, slot, order, a, acc, wc);
 
-  // split rows: publish the partial sum; the last unit to arrive combines
+  // split rows: the units' partial sums are added up a tree of fan-in
+  // kFanIn (levels L = 0 .. T, level 0 = the units, one node at level T);
+  // the last child to arrive at a node sums the node's children in index
+  // order and climbs, so the sum's association is fixed by the tree alone
   bool finish = active;
-  const bool split = active && nch > 1;
+  const bool split = active && w.nch > 1;
   if (__any(split)) {
+    const uint64_t tc = A.wave_stats ? clock64() : 0;
+    const int64_t base = split ? A.hub_base[u] : 0;
+    bool climbing = split;
+    finish = !split && active;
+    int32_t node = w.c, count = w.nch, off = 0;  // current node and its level's size/offset
     if (split) {
-      float* part = A.hub_part + (A.hub_base[u] + c) * A.d;
+      float* part = A.hub_part + (base + node) * A.d;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e0 = (r * G + l) * V;
@@ -223,41 +325,67 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, int32_t p, int3
       }
     }
     drain_memory();
-    uint32_t old = 0;
-    if (split && l == 0)
-      old = __hip_atomic_fetch_add(A.hub_cnt + u, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    old = __shfl(old, slot * G, 64);
-    compiler_fence();
-    if (split) {
-      finish = (old + 1u) % static_cast<uint32_t>(nch) == 0u;
-      if (finish) {
+    while (__any(climbing)) {
+      const int32_t parent = node / kFanIn;
+      const int32_t pcount = (count + kFanIn - 1) / kFanIn;
+      const int32_t poff = off + count;
+      const int32_t first = parent * kFanIn;
+      const int32_t nchild = count - first < kFanIn ? count - first : kFanIn;
+      uint32_t old = 0;
+      if (climbing && l == 0)
+        old = __hip_atomic_fetch_add(A.hub_cnt + base + poff + parent, 1u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      old = __shfl(old, slot * G, 64);
+      compiler_fence();
+      const bool last = climbing && (old + 1u) % static_cast<uint32_t>(nchild) == 0u;
+      if (last) {
+        float t[kFanIn][R][V];
+        const float* kids = A.hub_part + (base + off + first) * A.d;
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int i = 0; i < V; ++i) acc[r][i] = 0.0f;
-        const float* part0 = A.hub_part + A.hub_base[u] * A.d;
-        for (int i = 0; i < nch; ++i) {
+        for (int j = 0; j < kFanIn; ++j)
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int e0 = (r * G + l) * V;
-            if (e0 < A.d) {
-              float t[V];
-              load_coherent<V, false>(part0 + static_cast<int64_t>(i) * A.d + e0, t);
+            if (j < nchild && e0 < A.d) {
+              load_coherent<V, false>(kids + static_cast<int64_t>(j) * A.d + e0, t[j][r]);
+            } else {
 #pragma unroll
-              for (int q = 0; q < V; ++q) acc[r][q] += t[q];
+              for (int q = 0; q < V; ++q) t[j][r][q] = 0.0f;
             }
           }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < V; ++q) acc[r][q] = t[0][r][q];
+#pragma unroll
+        for (int j = 1; j < kFanIn; ++j)
+          if (j < nchild) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int q = 0; q < V; ++q) acc[r][q] += t[j][r][q];
+          }
+      }
+      climbing = last && pcount > 1;
+      if (last && pcount == 1) finish = true;
+      if (climbing) {
+        float* part = A.hub_part + (base + poff + parent) * A.d;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e0 = (r * G + l) * V;
+          if (e0 < A.d) store_coherent_f32<V>(part + e0, acc[r]);
         }
       }
+      drain_memory();
+      node = parent;
+      count = pcount;
+      off = poff;
     }
+    if (A.wave_stats) wc.combine += clock64() - tc;
   }
 
-  // repulsion from the batch's shared negatives (second inner loop)
-  if (A.s > 0)
-    accumulate_list<G, V, R, BF16>(A, finish, true, A.negs + static_cast<int64_t>(k) * A.s, A.s,
-                                   k, wait, l, slot, a, acc);
-
   // the step of Eq. 10 and its publication
+  const uint64_t tp = A.wave_stats ? clock64() : 0;
   if (finish) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -281,16 +409,27 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, int32_t p, int3
     }
   }
   drain_memory();
-  if (finish && l == 0) st_coherent_u32(A.stamp + u, A.gen);
+  if (finish && l == 0) st_coherent_u32(A.word + u, static_cast<uint32_t>(w.k) | kPublished);
+  if (A.trace && finish && l == 0) {
+    A.trace[2 * static_cast<int64_t>(u)] = static_cast<uint32_t>(wc.last_wait_end);
+    A.trace[2 * static_cast<int64_t>(u) + 1] = static_cast<uint32_t>(wall_clock64());
+  }
+  if (A.wave_stats) {
+    wc.publish += clock64() - tp;
+    wc.groups += 1;
+  }
 }
 
 template <int G, int V, int R, bool BF16>
 __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
   constexpr int S = 64 / G;
+  // per-wave LDS for the reordered entries of a step (64 * kIdxPerLane words)
+  __shared__ uint32_t order_lds[4][64 * ListShape<G>::kIdxPerLane];
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int nwaves = gridDim.x * (blockDim.x >> 6);
+  uint32_t* order = order_lds[threadIdx.x >> 6];
   int gbeg, gend;
   bool wait;
   if (A.strict_batch >= 0) {
@@ -302,9 +441,31 @@ __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
     gend = *A.ngroups;
     wait = true;
   }
-  for (int g = gbeg + wave; g < gend; g += nwaves) {
-    const int2 pc = A.tmap[static_cast<int64_t>(g) * S + slot];
-    process_unit<G, V, R, BF16>(A, pc.x, pc.y, l, slot, wait);
+  WaveCounters wc;
+  const uint64_t t_start = A.wave_stats ? clock64() : 0;
+  int g = gbeg + wave;
+  Unit cur{};
+  cur.u = -1;
+  if (g < gend) cur = A.units[static_cast<int64_t>(g) * S + slot];
+  while (g < gend) {
+    // fetch the next group's unit while this one is processed
+    const int gn = g + nwaves;
+    Unit nxt{};
+    nxt.u = -1;
+    if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
+    process_unit<G, V, R, BF16>(A, cur, l, slot, wait, order, wc);
+    cur = nxt;
+    g = gn;
+  }
+  if (A.wave_stats && lane == 0) {
+    uint64_t* o = A.wave_stats + static_cast<int64_t>(wave) * kWaveStats;
+    o[kStatCycles] = clock64() - t_start;
+    o[kStatWaitCycles] = wc.wait;
+    o[kStatCombineCycles] = wc.combine;
+    o[kStatGroups] = wc.groups;
+    o[kStatPolls] = wc.polls;
+    o[kStatWaits] = wc.waits;
+    o[kStatPublishCycles] = wc.publish;
   }
 }
 
@@ -316,8 +477,8 @@ template <int G, int V, int R, bool BF16>
 __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
   using T = typename Elem<BF16>::T;
   constexpr int S = 64 / G;
-  constexpr int K = ListShape<G>::kIdxPerLane;
-  constexpr int kStep = ListShape<G>::kStep;
+  constexpr int K = LossShape<G>::kIdxPerLane;
+  constexpr int kStep = LossShape<G>::kStep;
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
   const int64_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);

@@ -56,7 +56,7 @@ def good(**over):
 
 def test_defaults_and_workspace():
     p = good()
-    assert p.batch == 384 and p.s == 5 and abs(p.lr0 - 0.02) < 1e-9 and p.chunk == 128
+    assert p.batch == 384 and p.s == 5 and abs(p.lr0 - 0.02) < 1e-9 and p.chunk == 32
     w128 = f2v.workspace_size(p)
     w256 = f2v.workspace_size(good(d=256))
     assert w256 > w128 > 1000 * 128 * 4
@@ -64,7 +64,7 @@ def test_defaults_and_workspace():
 
 
 @pytest.mark.parametrize("field,value,status", [
-    ("n", 0, "F2V_E_INVALID_ARG"), ("n", 2**31, "F2V_E_INVALID_ARG"), ("d", 0, "F2V_E_INVALID_ARG"),
+    ("n", 0, "F2V_E_INVALID_ARG"), ("n", 2**29, "F2V_E_INVALID_ARG"), ("d", 0, "F2V_E_INVALID_ARG"),
     ("d", 1025, "F2V_E_INVALID_ARG"), ("d", 130, "F2V_E_UNSUPPORTED"), ("d", 65, "F2V_E_UNSUPPORTED"),
     ("batch", 0, "F2V_E_INVALID_ARG"), ("s", -1, "F2V_E_INVALID_ARG"), ("s", 65, "F2V_E_INVALID_ARG"),
     ("force", 2, "F2V_E_INVALID_ARG"), ("precision", 3, "F2V_E_INVALID_ARG"), ("lr0", 0.0, "F2V_E_INVALID_ARG"),
