@@ -49,6 +49,21 @@ def algorithmic_bytes(n: int, nnz: int, d: int, b: int, s: int, precision: str) 
     return nnz * (4 + 4 * d) + n * (8 * d + 12) + nb * s * 4 * d
 
 
+def recorded_traffic(workload: str, precision: str):
+    """HBM bytes per update launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a device
+    copy of known size), or None if they were taken on other kernel sources."""
+    from paper_2009_10035_amd.srchash import source_hash
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"k_update_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(g, Z0, p, seconds_target: float = 12.0) -> dict:
     """Time the FP64 oracle (as it stands) on the host over the first batches
     of epoch 0, growing the sample until it takes about `seconds_target`."""
@@ -76,7 +91,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict"])
+    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict", "dynamic"])
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -142,6 +157,7 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB copied 3 times")
+    traffic = recorded_traffic(args.workload, p["precision"])
     out = {
         "metric": "edge+negative updates/sec at 1 MI355X",
         "value": value,
@@ -160,7 +176,7 @@ def main() -> int:
                    "precision": p["precision"], "schedule": args.schedule,
                    "updates_per_epoch": updates},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_update", "kernel_ms": kern_ms, "epoch_ms": epoch_ms,
                      "algorithmic_bytes_per_launch": nbytes},
         "loss_after": loss[0],

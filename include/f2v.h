@@ -65,11 +65,16 @@ typedef enum { F2V_FORCE_SIGMOID = 0, F2V_FORCE_STUDENT_T = 1 } f2v_force;
 typedef enum { F2V_FP32 = 0, F2V_BF16 = 1 } f2v_precision;
 typedef enum { F2V_LR_CONST = 0, F2V_LR_LINEAR = 1 } f2v_lr_schedule;
 typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
-/* Device scheduling of one epoch; both give bit-identical results.
- * DATAFLOW: one persistent launch per epoch, batches overlap on the device and
- *   a vertex row is read only once the batch that updates it has published it.
- * STRICT: one launch per batch, batches separated by the stream order. */
-typedef enum { F2V_SCHED_DATAFLOW = 0, F2V_SCHED_STRICT = 1 } f2v_schedule;
+/* Device scheduling of one epoch; all give bit-identical results.
+ * DATAFLOW: one persistent launch per epoch (cooperative, sized to the
+ *   device's occupancy); batches overlap on the device and a vertex row is read
+ *   only once the batch that updates it has published it; work is assigned to
+ *   waves statically in batch order.
+ * STRICT: one launch per batch, batches separated by the stream order.
+ * DYNAMIC: as DATAFLOW, but running waves claim work in batch order from a
+ *   counter, so the launch needs no co-residency and its grid is sized to the
+ *   graph; for many concurrent jobs on one device (the server). */
+typedef enum { F2V_SCHED_DATAFLOW = 0, F2V_SCHED_STRICT = 1, F2V_SCHED_DYNAMIC = 2 } f2v_schedule;
 
 typedef struct {
     int64_t n;            /* vertices, >= 1, < 2^29 - 1 */

@@ -26,7 +26,7 @@ FORCE = {"sigmoid": 0, "student_t": 1}
 PRECISION = {"fp32": 0, "bf16": 1}
 LR_SCHEDULE = {"const": 0, "linear": 1}
 PERM = {"random": 0, "identity": 1}
-SCHEDULE = {"dataflow": 0, "strict": 1}
+SCHEDULE = {"dataflow": 0, "strict": 1, "dynamic": 2}
 
 
 class F2VError(RuntimeError):

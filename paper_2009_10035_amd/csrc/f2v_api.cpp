@@ -30,7 +30,7 @@ thread_local std::string g_error;
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, ucnt, uoff, negs, btot, breal, bstart, ngroups, units,
       hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part, loss_out,
-      wave_stats, trace, total;
+      wave_stats, trace, ticket, total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
 
@@ -75,6 +75,7 @@ Layout layout_of(const f2v_params& p) {
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
   L.trace = take(size_t(n) * 8);
+  L.ticket = take(4);
   L.total = off;
   return L;
 }
@@ -110,8 +111,9 @@ f2v_status validate(const f2v_params* p, std::string* msg) {
     return fail(msg, F2V_E_INVALID_ARG, "linear schedule needs total_epochs >= 1");
   if (p->perm_mode != F2V_PERM_RANDOM && p->perm_mode != F2V_PERM_IDENTITY)
     return fail(msg, F2V_E_INVALID_ARG, "perm_mode must be random or identity");
-  if (p->schedule != F2V_SCHED_DATAFLOW && p->schedule != F2V_SCHED_STRICT)
-    return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow or strict");
+  if (p->schedule != F2V_SCHED_DATAFLOW && p->schedule != F2V_SCHED_STRICT &&
+      p->schedule != F2V_SCHED_DYNAMIC)
+    return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow, strict or dynamic");
   if (p->chunk < 0 || p->chunk > kMaxChunk) return fail(msg, F2V_E_INVALID_ARG, "chunk must be in [0, 2^20]");
   const Layout L = layout_of(*p);
   if (L.tmap_cap >= (int64_t{1} << 31)) return fail(msg, F2V_E_INVALID_ARG, "too many work units for int32 tickets");
@@ -133,6 +135,7 @@ struct f2v_ctx {
   int cur = 0;
   const Variant* var = nullptr;
   int update_grid = 0;
+  int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit or the job's size
   int cus = 0;
   bool cooperative = true;  // launch the dataflow kernel with the co-residency guarantee
   bool diagnostics = false; // collect per-wave counters in dataflow epochs
@@ -266,6 +269,14 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   // profilers do not support cooperative launches); the grid is still sized to
   // the occupancy limit, and a wait that cannot complete ends at its bound.
   if (const char* env = std::getenv("F2V_COOPERATIVE")) c->cooperative = std::atoi(env) != 0;
+  {
+    // enough waves for about four groups each, at most the occupancy limit
+    const int64_t groups = (L.tmap_cap + slots_of(c->var) - 1) / slots_of(c->var);
+    int64_t blocks = (groups + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64));
+    if (blocks < 1) blocks = 1;
+    if (blocks > c->update_grid) blocks = c->update_grid;
+    c->dynamic_grid = static_cast<int>(blocks);
+  }
   for (hipEvent_t& e : c->ev)
     if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
 
@@ -325,6 +336,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.bstart = c->at<int32_t>(L.bstart);
   sa.units = c->at<f2v::Unit>(L.units);
   sa.ngroups = c->at<int32_t>(L.ngroups);
+  sa.ticket = c->at<uint32_t>(L.ticket);
   sa.n = p.n;
   sa.b = p.batch;
   sa.s = p.s;
@@ -368,14 +380,22 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
   A.spin_limit = kSpinLimit;
+  A.ticket = nullptr;
+  A.claim = 1;
   A.wave_stats = nullptr;
   A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
-  if (c->diagnostics && p.schedule == F2V_SCHED_DATAFLOW && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {
+  if (c->diagnostics && p.schedule != F2V_SCHED_STRICT && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {
     A.wave_stats = c->at<uint64_t>(L.wave_stats);
     c->stat_waves = int64_t(c->update_grid) * (kBlock / 64);
   }
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
-  if (p.schedule == F2V_SCHED_DATAFLOW) {
+  if (p.schedule == F2V_SCHED_DYNAMIC) {
+    A.strict_batch = -1;
+    A.ticket = c->at<uint32_t>(L.ticket);
+    A.claim = 1;
+    void* args[] = {&A};
+    HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
+  } else if (p.schedule == F2V_SCHED_DATAFLOW) {
     A.strict_batch = -1;
     void* args[] = {&A};
     if (c->cooperative)

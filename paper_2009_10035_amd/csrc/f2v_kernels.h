@@ -46,6 +46,8 @@ struct EpochArgs {
   float lr, eps;
   int32_t strict_batch;     // >= 0: process only this batch, no waits
   uint32_t spin_limit;      // bound on polls of one dependency wait
+  uint32_t* ticket;         // non-null: waves claim groups from this counter
+  int32_t claim;            // groups per claim
 };
 
 // Prologue of an epoch (random partition, negatives, work units).
@@ -61,6 +63,7 @@ struct SetupArgs {
   int32_t* bstart;          // [nb+1]
   Unit* units;
   int32_t* ngroups;
+  uint32_t* ticket;         // claim counter of the dynamic schedule (reset here)
   int64_t n;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave
   uint64_t seed;

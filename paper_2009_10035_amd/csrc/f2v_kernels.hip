@@ -97,6 +97,7 @@ __global__ void k_batch_starts(SetupArgs A) {
   if (threadIdx.x == 0) {
     A.bstart[A.nb] = static_cast<int32_t>(carry);
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
+    *A.ticket = 0u;
   }
 }
 

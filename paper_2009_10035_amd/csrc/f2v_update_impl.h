@@ -443,19 +443,34 @@ __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
   }
   WaveCounters wc;
   const uint64_t t_start = A.wave_stats ? clock64() : 0;
-  int g = gbeg + wave;
-  Unit cur{};
-  cur.u = -1;
-  if (g < gend) cur = A.units[static_cast<int64_t>(g) * S + slot];
-  while (g < gend) {
-    // fetch the next group's unit while this one is processed
-    const int gn = g + nwaves;
-    Unit nxt{};
-    nxt.u = -1;
-    if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
-    process_unit<G, V, R, BF16>(A, cur, l, slot, wait, order, wc);
-    cur = nxt;
-    g = gn;
+  if (A.ticket) {
+    // dynamic: claim `claim` consecutive groups at a time, in batch order
+    while (true) {
+      uint32_t g0 = 0;
+      if (lane == 0) g0 = atomicAdd(A.ticket, static_cast<uint32_t>(A.claim));
+      g0 = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(g0)));
+      if (g0 >= static_cast<uint32_t>(gend)) break;
+      const int g1 = static_cast<int>(g0) + A.claim < gend ? static_cast<int>(g0) + A.claim : gend;
+      for (int g = static_cast<int>(g0); g < g1; ++g) {
+        const Unit w = A.units[static_cast<int64_t>(g) * S + slot];
+        process_unit<G, V, R, BF16>(A, w, l, slot, wait, order, wc);
+      }
+    }
+  } else {
+    int g = gbeg + wave;
+    Unit cur{};
+    cur.u = -1;
+    if (g < gend) cur = A.units[static_cast<int64_t>(g) * S + slot];
+    while (g < gend) {
+      // fetch the next group's unit while this one is processed
+      const int gn = g + nwaves;
+      Unit nxt{};
+      nxt.u = -1;
+      if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
+      process_unit<G, V, R, BF16>(A, cur, l, slot, wait, order, wc);
+      cur = nxt;
+      g = gn;
+    }
   }
   if (A.wave_stats && lane == 0) {
     uint64_t* o = A.wave_stats + static_cast<int64_t>(wave) * kWaveStats;

@@ -40,7 +40,7 @@ def test_negatives_bit_identical(n, b, s):
         assert np.array_equal(gpu, oracle.negatives(n, b, s, seed, epoch))
 
 
-@pytest.mark.parametrize("schedule", ["dataflow", "strict"])
+@pytest.mark.parametrize("schedule", ["dataflow", "strict", "dynamic"])
 def test_er1k_free_running_20_epochs(schedule):
     g, p = gg.workload("er1k")
     Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
@@ -78,8 +78,9 @@ def test_dataflow_equals_strict_and_oracle(maker, chunk, d, force):
     Z0 = gg.init_embedding(g.n, d, 3)
     a = gpu_run(g, Z0, p, 2, schedule="dataflow")
     b = gpu_run(g, Z0, p, 2, schedule="strict")
-    for x, y in zip(a, b):
-        assert np.array_equal(x, y)
+    c = gpu_run(g, Z0, p, 2, schedule="dynamic")
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
     ref = oracle.epoch(g, Z0, 0, oracle_params(p))
     assert rel_fro(a[0], ref) <= TOL
 
@@ -152,8 +153,9 @@ def test_edge_cases(case):
     for x, y in zip(got, ref):
         assert rel_fro(x, y) <= TOL, case
     got_s = gpu_run(g, Z0, p, 3, schedule="strict")
-    for x, y in zip(got, got_s):
-        assert np.array_equal(x, y), case
+    got_d = gpu_run(g, Z0, p, 3, schedule="dynamic")
+    for x, y, z in zip(got, got_s, got_d):
+        assert np.array_equal(x, y) and np.array_equal(x, z), case
 
 
 @pytest.mark.parametrize("force", ["sigmoid", "student_t"])
