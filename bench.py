@@ -31,7 +31,61 @@ WORKLOADS = {
     "sbm4m": "SBM n=4,000,000 in 64 blocks (c_in 24, c_out 6); d=128, BF16 rows + FP32 master, "
              "Student-t force, batch 384, s=10, lr 0.02",
     "rgg2m": "2-D random geometric graph n=2,000,000 avg degree 12; d=2, Student-t force, batch 384, s=5, lr 0.02",
+    "serve": "stream of embedding jobs with Poisson arrivals at 70% of the measured closed-loop capacity: "
+             "Chung-Lu graphs (n lognormal median 20k in [500, 500k], avg degree U[8,32]), d in {2,32,128} "
+             "(d=2 Student-t layout, else sigmoid), FP32/BF16 half each, 10 epochs, batch 384, s=5",
 }
+
+
+def serve_bench(args) -> int:
+    """Serving form: p50/p99 job latency and aggregate updates/s of a Poisson
+    stream of jobs, admitted by HBM footprint into concurrent slots."""
+    import torch
+    from paper_2009_10035_amd.serve import DeviceServer, make_job_stream, run_requests
+    t0 = time.perf_counter()
+    jobs = make_job_stream(args.jobs, rate=0.0, seed=args.seed)
+    log(f"built {len(jobs)} jobs from a pool of graphs ({time.perf_counter() - t0:.1f}s)")
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    # closed-loop capacity: a prefix of the stream, all arriving at once
+    calib = jobs[: min(len(jobs), args.calib_jobs)]
+    srv = DeviceServer(budget, args.slots)
+    out = run_requests(calib, srv, progress=log)
+    srv.close()
+    capacity = out["jobs"] / out["makespan"]
+    rate = 0.7 * capacity
+    log(f"closed-loop capacity {capacity:.1f} jobs/s on {len(calib)} jobs; arrival rate {rate:.1f} jobs/s")
+    rng = np.random.default_rng(args.seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(jobs)))
+    for j, a in zip(jobs, arrivals):
+        j.arrival = float(a)
+    srv = DeviceServer(budget, args.slots)
+    torch.cuda.synchronize()
+    out = run_requests(jobs, srv, progress=log)
+    srv.close()
+    rec = list(out["records"].values())
+    line = {
+        "metric": "p99 job latency (serving, 1 MI355X)",
+        "value": out["p99"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(jobs),
+        "warmup": len(calib),
+        "ms_per_step": out["makespan"] * 1e3 / max(len(jobs), 1),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["serve"], "name": "serve", "jobs": len(jobs), "slots": args.slots,
+                   "hbm_budget_gb": args.hbm_budget_gb, "arrival_rate_jobs_per_s": rate,
+                   "closed_loop_capacity_jobs_per_s": capacity},
+        "p50_s": out["p50"], "p99_s": out["p99"], "mean_s": out["mean"],
+        "updates_per_s": out["updates_per_s"], "makespan_s": out["makespan"],
+        "failed": out["failed"], "host_seconds": out["host_seconds"],
+        "mean_n": float(np.mean([r["n"] for r in rec])), "total_updates": out["updates"],
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if out["failed"] == 0 else 1
 
 
 def log(msg: str) -> None:
@@ -97,11 +151,18 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--jobs", type=int, default=2000, help="serve: jobs in the stream")
+    ap.add_argument("--calib-jobs", type=int, default=300, help="serve: jobs of the capacity run")
+    ap.add_argument("--slots", type=int, default=16, help="serve: concurrent jobs")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: HBM budget for jobs")
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("only --gpus 1 is supported: the update is measured on one MI355X")
         return 2
+    if args.workload == "serve":
+        return serve_bench(args)
     import torch
     import graphgen as gg
     import paper_2009_10035_amd as f2v

@@ -157,6 +157,12 @@ f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_m
 f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch,
                          int32_t *d_S, void *stream);
 
+/* A random initial embedding on the device: count floats uniform on
+ * [-scale, scale) (the method starts from a random Z; a U[-0.5, 0.5) start is
+ * scale 0.5).  Element i uses word i mod 4 of Philox(i div 4, 0, 0, 4) keyed by
+ * seed (24 high bits).  Asynchronous on `stream`. */
+f2v_status f2v_random_embedding(float *d_z, int64_t count, uint64_t seed, float scale, void *stream);
+
 /* Device time of the most recent f2v_epoch's update kernel(s) in ms, measured
  * with HIP events on the context's stream (prologue excluded).  Synchronises. */
 f2v_status f2v_last_epoch_ms(f2v_ctx *ctx, float *update_ms, float *total_ms);
@@ -177,6 +183,60 @@ f2v_status f2v_wave_stats(f2v_ctx *ctx, uint64_t *out, int64_t cap_waves, int64_
  * it did not wait), out[2u+1] = publication of u's new row.  `out` is host
  * memory for 2n uint32.  Synchronises. */
 f2v_status f2v_vertex_trace(f2v_ctx *ctx, uint32_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Serving: many embedding jobs on one device.
+ *
+ * A server owns `max_slots` slots, each with its own HIP stream (default
+ * priority), and admits jobs while a slot is free and the sum of the admitted
+ * jobs' footprints stays within `hbm_budget` bytes.  The caller allocates each
+ * job's device memory (CSR, initial embedding, workspace) after checking that
+ * the server can admit it, and keeps it alive until the job is reported done.
+ * Jobs overlap on the device: every job runs the dynamic schedule (no
+ * co-residency needed).  A job's result does not depend on the other jobs
+ * running with it (bit-identical to running it alone).
+ */
+typedef struct f2v_server f2v_server;
+
+/* Device bytes of one job: CSR (8(n+1) + 4 nnz), embedding (4 n d) and
+ * workspace (f2v_workspace_size).  Host only. */
+f2v_status f2v_footprint(const f2v_params *p, size_t *bytes);
+
+/* Create a server (1 <= max_slots <= 256, hbm_budget > 0).  Allocates the
+ * slots' streams and a small pinned host array for completion records. */
+f2v_status f2v_server_create(size_t hbm_budget, int32_t max_slots, f2v_server **out);
+
+/* Admit one job of `epochs` epochs (0 .. epochs-1) with params p
+ * (p->schedule must be F2V_SCHED_DYNAMIC) on the caller's device buffers (as
+ * f2v_init).  F2V_E_BUSY if no slot is free or the footprint does not fit the
+ * remaining budget (the caller queues the job and retries).  pack == 0: the
+ * run is issued at once on the slot's stream.  pack != 0: the job waits for
+ * f2v_server_flush, which captures all waiting jobs into one HIP graph (each
+ * job on its own stream) and starts it with one launch.  On success *job_id
+ * identifies the job.  Validates the CSR (synchronises the slot's stream). */
+f2v_status f2v_server_submit(f2v_server *s, const f2v_params *p, const int64_t *d_rowptr,
+                             const int32_t *d_colidx, float *d_z, void *d_ws, size_t ws_bytes,
+                             int32_t epochs, int32_t pack, uint64_t *job_id);
+
+/* Launch the packed jobs submitted since the last flush as one graph. */
+f2v_status f2v_server_flush(f2v_server *s);
+
+/* Non-blocking: report up to `cap` jobs that finished (done[i], status[i] =
+ * F2V_OK or F2V_E_TIMEOUT), release their slots and budget.  A finished
+ * job's embedding buffer holds its result (the FP32 master in the bf16 form). */
+f2v_status f2v_server_poll(f2v_server *s, uint64_t *done, int32_t *status, int32_t cap,
+                           int32_t *n_done);
+
+/* Current occupancy (any pointer may be NULL). */
+f2v_status f2v_server_query(f2v_server *s, int32_t *active, int32_t *free_slots,
+                            size_t *used_bytes, size_t *budget_bytes);
+
+/* Flush, then wait until every submitted job has finished on the device
+ * (their completions are still reported by f2v_server_poll). */
+f2v_status f2v_server_drain(f2v_server *s);
+
+f2v_status f2v_server_destroy(f2v_server *s);
+const char *f2v_server_last_error(const f2v_server *s);
 
 #ifdef __cplusplus
 }

@@ -11,10 +11,10 @@ import ctypes
 
 import torch
 
-from ._binding import (EXPORTS, F2VError, Params, check, load, make_params, workspace_size)
+from ._binding import (EXPORTS, F2VError, Params, check, footprint, load, make_params, workspace_size)
 
-__all__ = ["Trainer", "F2VError", "Params", "make_params", "workspace_size", "partition",
-           "negatives", "load", "EXPORTS"]
+__all__ = ["Trainer", "F2VError", "Params", "make_params", "workspace_size", "footprint", "partition",
+           "negatives", "random_embedding", "load", "EXPORTS"]
 
 
 def _stream_handle(device) -> int:
@@ -124,6 +124,14 @@ def partition(n: int, seed: int, epoch: int, mode: str = "random", device="cuda"
     out = torch.empty(n, dtype=torch.int32, device=device)
     check(load().f2v_partition(n, seed, epoch, 1 if mode == "identity" else 0, out.data_ptr(),
                                _stream_handle(out.device)))
+    return out
+
+
+def random_embedding(n: int, d: int, seed: int, scale: float = 0.5, device="cuda") -> torch.Tensor:
+    """Uniform initial embedding on [-scale, scale) drawn on the device (float32 [n, d])."""
+    out = torch.empty((n, d), dtype=torch.float32, device=device)
+    check(load().f2v_random_embedding(out.data_ptr() if out.numel() else None, n * d, seed, scale,
+                                      _stream_handle(out.device)))
     return out
 
 

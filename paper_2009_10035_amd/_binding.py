@@ -17,7 +17,9 @@ EXPORTS = (
     "f2v_default_params", "f2v_workspace_size", "f2v_init", "f2v_epoch", "f2v_loss",
     "f2v_sync_embedding", "f2v_check", "f2v_destroy", "f2v_status_string", "f2v_last_error",
     "f2v_partition", "f2v_negatives", "f2v_last_epoch_ms", "f2v_set_diagnostics", "f2v_wave_stats",
-    "f2v_vertex_trace",
+    "f2v_vertex_trace", "f2v_footprint", "f2v_server_create", "f2v_server_submit",
+    "f2v_server_flush", "f2v_server_poll", "f2v_server_query", "f2v_server_drain",
+    "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",
@@ -93,6 +95,25 @@ def load(build_if_missing: bool = True):
     L.f2v_wave_stats.restype = st
     L.f2v_vertex_trace.argtypes = [P, P]
     L.f2v_vertex_trace.restype = st
+    L.f2v_footprint.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+    L.f2v_footprint.restype = st
+    L.f2v_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
+    L.f2v_server_create.restype = st
+    L.f2v_server_submit.argtypes = [P, PP, P, P, P, P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.f2v_server_submit.restype = st
+    for name in ("f2v_server_flush", "f2v_server_drain", "f2v_server_destroy"):
+        getattr(L, name).argtypes = [P]
+        getattr(L, name).restype = st
+    L.f2v_server_poll.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.f2v_server_poll.restype = st
+    L.f2v_server_query.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    L.f2v_server_query.restype = st
+    L.f2v_random_embedding.argtypes = [P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, P]
+    L.f2v_random_embedding.restype = st
+    L.f2v_server_last_error.argtypes = [P]
+    L.f2v_server_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -118,6 +139,13 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
         p.chunk = chunk
     p.seed = seed
     return p
+
+
+def footprint(p: Params) -> int:
+    """Device bytes of one job: CSR, embedding and workspace."""
+    out = ctypes.c_size_t(0)
+    check(load().f2v_footprint(ctypes.byref(p), ctypes.byref(out)))
+    return int(out.value)
 
 
 def workspace_size(p: Params) -> int:

@@ -27,6 +27,7 @@ SOURCES = [
     "f2v_variants_bf16_v2.hip",
     "f2v_variants.cpp",
     "f2v_api.cpp",
+    "f2v_server.cpp",
 ]
 HEADERS = ["f2v_device.h", "f2v_kernels.h", "f2v_update_impl.h", "../../include/f2v.h"]
 

@@ -28,7 +28,7 @@ constexpr int64_t kMaxStatWaves = 16384;
 thread_local std::string g_error;
 
 struct Layout {
-  size_t zbuf1, bbuf0, bbuf1, perm, word, ucnt, uoff, negs, btot, breal, bstart, ngroups, units,
+  size_t zbuf1, bbuf0, bbuf1, perm, word, ucnt, uoff, dkey, order, negs, btot, breal, bstart, ngroups, units,
       hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part, loss_out,
       wave_stats, trace, ticket, total;
   int64_t nb, tmap_cap, hub_slot_cap;
@@ -44,8 +44,8 @@ Layout layout_of(const f2v_params& p) {
   const int32_t chunk = chunk_of(p);
   L.nb = (n + p.batch - 1) / p.batch;
   // a split row of degree deg > chunk has m = ceil(deg/chunk) < 2 deg / chunk
-  // units, and its combining tree at most 1.5 m nodes
-  L.hub_slot_cap = 3 * ((p.nnz + chunk - 1) / chunk) + 8;
+  // units, and its combining tree (fan-in >= 4) at most 1.6 m < 2 m nodes
+  L.hub_slot_cap = 4 * ((p.nnz + chunk - 1) / chunk) + 8;
   // tickets: one per unit, plus at most 63 padding tickets per batch
   L.tmap_cap = n + p.nnz / chunk + L.nb * 63 + 64;
   size_t off = 0;
@@ -58,6 +58,8 @@ Layout layout_of(const f2v_params& p) {
   L.word = take(size_t(n) * 4);
   L.ucnt = take(size_t(n) * 4);
   L.uoff = take(size_t(n) * 4);
+  L.dkey = take(size_t(n) * 4);
+  L.order = take(size_t(n) * 4);
   L.negs = take(size_t(L.nb) * (p.s > 0 ? p.s : 1) * 4);
   L.btot = take(size_t(L.nb) * 4);
   L.breal = take(size_t(L.nb) * 4);
@@ -142,6 +144,9 @@ struct f2v_ctx {
   int64_t stat_waves = 0;   // waves of the last epoch with counters
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   bool timed = false;
+  bool record_events = true;  // off while a server captures the context's work into a graph
+  int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
+  int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
   std::string err;
 
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -184,6 +189,14 @@ void f2v_default_params(f2v_params* p) {
   p->schedule = F2V_SCHED_DATAFLOW;
   p->chunk = kDefaultChunk;
   p->seed = 0;
+}
+
+f2v_status f2v_footprint(const f2v_params* p, size_t* bytes) {
+  f2v_status st = validate(p, nullptr);
+  if (st != F2V_OK) return st;
+  if (!bytes) return fail(nullptr, F2V_E_INVALID_ARG, "bytes is NULL");
+  *bytes = size_t(p->n + 1) * 8 + size_t(p->nnz) * 4 + size_t(p->n) * p->d * 4 + layout_of(*p).total;
+  return F2V_OK;
 }
 
 f2v_status f2v_workspace_size(const f2v_params* p, size_t* bytes) {
@@ -269,6 +282,11 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   // profilers do not support cooperative launches); the grid is still sized to
   // the occupancy limit, and a wait that cannot complete ends at its bound.
   if (const char* env = std::getenv("F2V_COOPERATIVE")) c->cooperative = std::atoi(env) != 0;
+  if (const char* env = std::getenv("F2V_FAN_IN")) {
+    const int x = std::atoi(env);
+    if (x >= 4 && x <= 64) c->fan_in = x;
+  }
+  if (const char* env = std::getenv("F2V_SORT")) c->sort = std::atoi(env) != 0;
   {
     // enough waves for about four groups each, at most the occupancy limit
     const int64_t groups = (L.tmap_cap + slots_of(c->var) - 1) / slots_of(c->var);
@@ -300,7 +318,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     return bail(F2V_E_BAD_GRAPH, m);
   }
   int64_t hub_total = 0;
-  if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.hub_base),
+  if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, L.hub_slot_cap, s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
@@ -322,10 +340,13 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   const hipStream_t s = c->stream;
   const bool bf16 = p.precision == F2V_BF16;
   const int slots = slots_of(c->var);
-  HIP_TRY(c, hipEventRecord(c->ev[0], s));
+  if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[0], s));
 
   SetupArgs sa{};
   sa.rowptr = c->rowptr;
+  sa.colidx = c->colidx;
+  sa.dkey = c->at<int32_t>(L.dkey);
+  sa.order = c->at<int32_t>(L.order);
   sa.perm = c->at<int32_t>(L.perm);
   sa.word = c->at<uint32_t>(L.word);
   sa.ucnt = c->at<int32_t>(L.ucnt);
@@ -346,6 +367,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.seed = p.seed;
   sa.epoch = static_cast<uint32_t>(epoch);
   sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
+  sa.sort = c->sort;
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;
@@ -382,13 +404,14 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.spin_limit = kSpinLimit;
   A.ticket = nullptr;
   A.claim = 1;
+  A.fan_in = c->fan_in;
   A.wave_stats = nullptr;
   A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
   if (c->diagnostics && p.schedule != F2V_SCHED_STRICT && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {
     A.wave_stats = c->at<uint64_t>(L.wave_stats);
     c->stat_waves = int64_t(c->update_grid) * (kBlock / 64);
   }
-  HIP_TRY(c, hipEventRecord(c->ev[1], s));
+  if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (p.schedule == F2V_SCHED_DYNAMIC) {
     A.strict_batch = -1;
     A.ticket = c->at<uint32_t>(L.ticket);
@@ -413,8 +436,10 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
       HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(grid), dim3(kBlock), args, 0, s));
     }
   }
-  HIP_TRY(c, hipEventRecord(c->ev[2], s));
-  c->timed = true;
+  if (c->record_events) {
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    c->timed = true;
+  }
   c->cur = 1 - c->cur;
   return F2V_OK;
 }
@@ -508,8 +533,8 @@ f2v_status f2v_loss(f2v_ctx* c, double out[3]) {
 f2v_status f2v_sync_embedding(f2v_ctx* c) {
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
   if (c->p.precision == F2V_FP32 && c->cur != 0) {
-    HIP_TRY(c, hipMemcpyAsync(c->zbuf[0], c->zbuf[c->cur], size_t(c->p.n) * c->p.d * sizeof(float),
-                              hipMemcpyDeviceToDevice, c->stream));
+    // a copy kernel rather than hipMemcpyAsync, so that the call can be captured in a graph
+    HIP_TRY(c, f2v::launch_copy_f32(c->zbuf[0], c->zbuf[c->cur], c->p.n * int64_t(c->p.d), c->stream));
     c->cur = 0;
   }
   return F2V_OK;
@@ -536,6 +561,15 @@ f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_m
   return F2V_OK;
 }
 
+f2v_status f2v_random_embedding(float* d_z, int64_t count, uint64_t seed, float scale, void* stream) {
+  if (count < 0 || (count > 0 && !d_z)) return fail(nullptr, F2V_E_INVALID_ARG, "bad embedding buffer");
+  if (!std::isfinite(scale) || scale < 0.0f) return fail(nullptr, F2V_E_INVALID_ARG, "scale must be finite, >= 0");
+  if (count == 0) return F2V_OK;
+  hipError_t e = f2v::launch_random_embedding(d_z, count, seed, scale, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("random embedding: ") + hipGetErrorString(e));
+  return F2V_OK;
+}
+
 f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch, int32_t* d_S,
                          void* stream) {
   if (n < 1 || n >= (int64_t{1} << 31) - 1) return fail(nullptr, F2V_E_INVALID_ARG, "n out of range");
@@ -548,3 +582,12 @@ f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int
 }
 
 }  // extern "C"
+
+namespace f2v {
+
+// Accessors for the server (f2v_server.cpp).
+void ctx_set_record_events(f2v_ctx* c, bool on) { c->record_events = on; }
+hipStream_t ctx_stream(const f2v_ctx* c) { return c->stream; }
+const uint32_t* ctx_err_word(const f2v_ctx* c) { return c->at<uint32_t>(c->L.err); }
+
+}  // namespace f2v

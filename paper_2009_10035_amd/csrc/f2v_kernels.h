@@ -48,15 +48,19 @@ struct EpochArgs {
   uint32_t spin_limit;      // bound on polls of one dependency wait
   uint32_t* ticket;         // non-null: waves claim groups from this counter
   int32_t claim;            // groups per claim
+  int32_t fan_in;           // fan-in of the combining tree of split rows
 };
 
 // Prologue of an epoch (random partition, negatives, work units).
 struct SetupArgs {
   const int64_t* rowptr;
+  const int32_t* colidx;
   int32_t* perm;            // position -> vertex
   uint32_t* word;           // vertex -> batch index (unpublished)
   int32_t* ucnt;            // position -> work units of that row
   int32_t* uoff;            // position -> unit offset inside its batch
+  int32_t* dkey;            // position -> latest earlier batch its row depends on (-1: none)
+  int32_t* order;           // positions of each batch, sorted by dkey (then position)
   int32_t* negs;
   int32_t* btot;            // [nb] unit count of each batch padded to the slot count
   int32_t* breal;           // [nb] unit count of each batch
@@ -71,6 +75,7 @@ struct SetupArgs {
   int32_t identity;
   int32_t feistel_half;
   uint32_t feistel_mask;
+  int32_t sort;             // order each batch's rows by readiness
 };
 
 struct LossArgs {
@@ -102,13 +107,18 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_t n, int64_t nnz,
                             uint32_t* flag, hipStream_t st);
-hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* hub_base,
-                           int64_t* scratch, int64_t* total, hipStream_t st);
+hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int32_t fan_in,
+                           int64_t* hub_base, int64_t* scratch, int64_t* total, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
 hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st);
 hipError_t launch_partition(int64_t n, uint64_t seed, uint32_t epoch, int identity, int32_t* perm,
                             hipStream_t st);
 hipError_t launch_negatives(int64_t n, int32_t b, int32_t s, uint64_t seed, uint32_t epoch,
                             int32_t* negs, hipStream_t st);
+hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStream_t st);
+hipError_t launch_random_embedding(float* z, int64_t count, uint64_t seed, float scale, hipStream_t st);
+// Completion record of a server job: copies the job's device error word and
+// then `seq` into host-visible memory rec[0..1] (rec[0] written last).
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, const uint32_t* err, hipStream_t st);
 
 }  // namespace f2v

@@ -53,20 +53,70 @@ __global__ void k_setup_positions(SetupArgs A) {
   }
 }
 
-// K2: one block per batch: unit offsets inside the batch, and the batch's
-// unit count padded to a multiple of the lane groups per wave.
+// K1b: 16 lanes per position: the latest earlier batch among the row's
+// neighbours (the batch whose publication it will wait for last).
+__global__ void k_readiness(SetupArgs A, const int32_t* colidx) {
+  const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t p = tid >> 4;
+  const int l = static_cast<int>(tid & 15);
+  int32_t best = -1;
+  if (p < A.n) {
+    const int32_t u = A.perm[p];
+    const int32_t k = static_cast<int32_t>(p / A.b);
+    const int64_t r1 = A.rowptr[u + 1];
+    for (int64_t e = A.rowptr[u] + l; e < r1; e += 16) {
+      const int32_t kb = static_cast<int32_t>(A.word[colidx[e]]);
+      if (kb < k && kb > best) best = kb;
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < 16; m <<= 1) {
+    const int32_t o = __shfl_xor(best, m, 64);
+    best = o > best ? o : best;
+  }
+  if (p < A.n && l == 0) A.dkey[p] = best;
+}
+
+// Batches larger than this keep position order (no readiness sort).
+constexpr int kSortMax = 2048;
+
+// K2: one block per batch: order the batch's positions by readiness (rows
+// whose dependencies are older first; ties by position), then the unit
+// offsets in that order, and the batch's unit count padded to a multiple of
+// the lane groups per wave.  Rows of one batch are independent, so the order
+// inside a batch changes no result.
 __global__ void k_batch_units(SetupArgs A) {
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
+  __shared__ int32_t keys[kSortMax];
   const int32_t k = blockIdx.x;
   const int64_t lo = static_cast<int64_t>(k) * A.b;
   const int64_t hi = lo + A.b < A.n ? lo + A.b : A.n;
+  const int32_t len = static_cast<int32_t>(hi - lo);
+  if (A.sort && len <= kSortMax) {
+    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) keys[i] = A.dkey[lo + i];
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+      const int32_t ki = keys[i];
+      int32_t rank = 0;
+      for (int32_t j = 0; j < len; ++j) {
+        const int32_t kj = keys[j];
+        rank += (kj < ki) || (kj == ki && j < i);
+      }
+      A.order[lo + rank] = static_cast<int32_t>(lo + i);
+    }
+  } else {
+    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) A.order[lo + i] = static_cast<int32_t>(lo + i);
+  }
+  __syncthreads();
+  __threadfence_block();
   int64_t carry = 0;
   for (int64_t base = lo; base < hi; base += blockDim.x) {
-    const int64_t p = base + threadIdx.x;
-    const int64_t c = p < hi ? A.ucnt[p] : 0;
+    const int64_t r = base + threadIdx.x;
+    const int32_t p = r < hi ? A.order[r] : 0;
+    const int64_t c = r < hi ? A.ucnt[p] : 0;
     const int64_t inc = block_inclusive_scan(c, lds);
-    if (p < hi) A.uoff[p] = static_cast<int32_t>(carry + inc - c);
+    if (r < hi) A.uoff[p] = static_cast<int32_t>(carry + inc - c);
     // the tile total is the last thread's inclusive value
     if (threadIdx.x == blockDim.x - 1) tile_total = inc;
     __syncthreads();
@@ -166,11 +216,11 @@ __global__ void k_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_
 }
 
 // Nodes of the combining tree of a split row with `units` units: the units,
-// then ceil(count / 8) nodes per level up to a single root.
-__device__ __forceinline__ int64_t tree_nodes(int64_t units) {
+// then ceil(count / fan_in) nodes per level up to a single root.
+__device__ __forceinline__ int64_t tree_nodes(int64_t units, int32_t fan_in) {
   int64_t total = units, count = units;
   while (count > 1) {
-    count = (count + 7) / 8;
+    count = (count + fan_in - 1) / fan_in;
     total += count;
   }
   return total;
@@ -178,11 +228,12 @@ __device__ __forceinline__ int64_t tree_nodes(int64_t units) {
 
 // Split-row slots (partial sums and arrival counters): per vertex, the nodes
 // of its combining tree if split, else 0.
-__global__ void k_hub_counts(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* out) {
+__global__ void k_hub_counts(const int64_t* rowptr, int64_t n, int32_t chunk, int32_t fan_in,
+                             int64_t* out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t deg = rowptr[i + 1] - rowptr[i];
-    out[i] = deg > chunk ? tree_nodes(units_of(deg, chunk)) : 0;
+    out[i] = deg > chunk ? tree_nodes(units_of(deg, chunk), fan_in) : 0;
   }
 }
 
@@ -265,6 +316,35 @@ __global__ void k_negatives(int64_t n, int64_t count, int32_t s, uint64_t seed, 
   }
 }
 
+__global__ void k_copy_f32(float* dst, const float* src, int64_t count) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Uniform initial embedding on [-scale, scale): element i takes the 24 high
+// bits of word (i & 3) of Philox(i_lo >> 2, i_hi, 0, tag 4) keyed by seed.
+__global__ void k_random_embedding(float* z, int64_t count, uint64_t seed, float scale) {
+  for (int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; q * 4 < count;
+       q += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint4 x = philox(static_cast<uint32_t>(q), static_cast<uint32_t>(static_cast<uint64_t>(q) >> 32), 0u,
+                           4u, seed);
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = q * 4 + j;
+      if (i < count) z[i] = (static_cast<float>(w[j] >> 8) * (1.0f / 16777216.0f) * 2.0f - 1.0f) * scale;
+    }
+  }
+}
+
+__global__ void k_signal(uint32_t* rec, uint32_t seq, const uint32_t* err) {
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(rec + 1, *err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(rec, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 int grid_for(int64_t work, int threads) {
   int64_t g = (work + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -277,6 +357,7 @@ int grid_for(int64_t work, int threads) {
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(a.n > nneg ? a.n : nneg, 256)), dim3(256), 0, st, a);
+  if (a.sort) hipLaunchKernelGGL(k_readiness, dim3((a.n * 16 + 255) / 256), dim3(256), 0, st, a, a.colidx);
   hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
   hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);
   hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0, st, a);
@@ -295,9 +376,10 @@ hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* hub_base,
-                           int64_t* scratch, int64_t* total, hipStream_t st) {
-  hipLaunchKernelGGL(k_hub_counts, dim3(grid_for(n, 256)), dim3(256), 0, st, rowptr, n, chunk, hub_base);
+hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int32_t fan_in,
+                           int64_t* hub_base, int64_t* scratch, int64_t* total, hipStream_t st) {
+  hipLaunchKernelGGL(k_hub_counts, dim3(grid_for(n, 256)), dim3(256), 0, st, rowptr, n, chunk, fan_in,
+                     hub_base);
   const int64_t nblocks = (n + kScanThreads - 1) / kScanThreads;
   hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanThreads), 0, st, hub_base, scratch, n);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scratch, nblocks, total);
@@ -329,6 +411,22 @@ hipError_t launch_negatives(int64_t n, int32_t b, int32_t s, uint64_t seed, uint
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_negatives, dim3(grid_for(count, 256)), dim3(256), 0, st, n, count, s, seed,
                      epoch, negs);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(count, 256)), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, const uint32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, st, host_rec, seq, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_random_embedding(float* z, int64_t count, uint64_t seed, float scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_random_embedding, dim3(grid_for((count + 3) / 4, 256)), dim3(256), 0, st, z, count, seed,
+                     scale);
   return hipGetLastError();
 }
 

@@ -64,10 +64,16 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
   uint32_t polls = 0;
   while (true) {
+    // each lane polls only its first pending entry: one load per lane and
+    // round keeps the poll traffic small while many waves wait
     any = false;
+    bool polled = false;
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      if (pend[q]) pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+      if (pend[q] && !polled) {
+        pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+        polled = pend[q];
+      }
       any |= pend[q];
     }
     if (!__any(any)) break;
@@ -77,9 +83,9 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
       break;
     }
     if ((polls & 255u) == 0 && ld_coherent_u32(A.err) != 0) break;
-    if (polls < 16) __builtin_amdgcn_s_sleep(1);
-    else if (polls < 64) __builtin_amdgcn_s_sleep(2);
-    else __builtin_amdgcn_s_sleep(8);
+    if (polls < 8) __builtin_amdgcn_s_sleep(1);
+    else if (polls < 32) __builtin_amdgcn_s_sleep(4);
+    else __builtin_amdgcn_s_sleep(16);
   }
   compiler_fence();
   if (A.wave_stats) {
@@ -139,8 +145,8 @@ constexpr uint32_t kEntPending = 1u << 30;
 constexpr uint32_t kEntNext = 1u << 31;
 constexpr uint32_t kEntNone = kEntVertex;  // no entry (vertex ids stay below it)
 
-// Fan-in of the combining tree of split rows.
-constexpr int kFanIn = 8;
+// Partial rows a combining-tree node loads at a time.
+constexpr int kLoadsInFlight = 8;
 
 // Forces between the group's row `a` and the entries of its unit's list:
 // `len` CSR neighbours from `nbr` (attraction), then `nneg` shared negatives
@@ -305,7 +311,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
                                  w.k, wait, l, slot, order, a, acc, wc);
 
   // split rows: the units' partial sums are added up a tree of fan-in
-  // kFanIn (levels L = 0 .. T, level 0 = the units, one node at level T);
+  // A.fan_in (levels L = 0 .. T, level 0 = the units, one node at level T);
   // the last child to arrive at a node sums the node's children in index
   // order and climbs, so the sum's association is fixed by the tree alone
   bool finish = active;
@@ -325,12 +331,13 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       }
     }
     drain_memory();
+    const int32_t fan = A.fan_in;
     while (__any(climbing)) {
-      const int32_t parent = node / kFanIn;
-      const int32_t pcount = (count + kFanIn - 1) / kFanIn;
+      const int32_t parent = node / fan;
+      const int32_t pcount = (count + fan - 1) / fan;
       const int32_t poff = off + count;
-      const int32_t first = parent * kFanIn;
-      const int32_t nchild = count - first < kFanIn ? count - first : kFanIn;
+      const int32_t first = parent * fan;
+      const int32_t nchild = count - first < fan ? count - first : fan;
       uint32_t old = 0;
       if (climbing && l == 0)
         old = __hip_atomic_fetch_add(A.hub_cnt + base + poff + parent, 1u, __ATOMIC_RELAXED,
@@ -339,32 +346,42 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       compiler_fence();
       const bool last = climbing && (old + 1u) % static_cast<uint32_t>(nchild) == 0u;
       if (last) {
-        float t[kFanIn][R][V];
+        // children in index order, kLoadsInFlight partial rows at a time
         const float* kids = A.hub_part + (base + off + first) * A.d;
+        for (int j0 = 0; j0 < nchild; j0 += kLoadsInFlight) {
+          float t[kLoadsInFlight][R][V];
 #pragma unroll
-        for (int j = 0; j < kFanIn; ++j)
+          for (int j = 0; j < kLoadsInFlight; ++j)
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int e0 = (r * G + l) * V;
-            if (j < nchild && e0 < A.d) {
-              load_coherent<V, false>(kids + static_cast<int64_t>(j) * A.d + e0, t[j][r]);
-            } else {
+            for (int r = 0; r < R; ++r) {
+              const int e0 = (r * G + l) * V;
+              if (j0 + j < nchild && e0 < A.d) {
+                load_coherent<V, false>(kids + static_cast<int64_t>(j0 + j) * A.d + e0, t[j][r]);
+              } else {
 #pragma unroll
-              for (int q = 0; q < V; ++q) t[j][r][q] = 0.0f;
+                for (int q = 0; q < V; ++q) t[j][r][q] = 0.0f;
+              }
             }
-          }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int q = 0; q < V; ++q) acc[r][q] = t[0][r][q];
-#pragma unroll
-        for (int j = 1; j < kFanIn; ++j)
-          if (j < nchild) {
+          if (j0 == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-              for (int q = 0; q < V; ++q) acc[r][q] += t[j][r][q];
+              for (int q = 0; q < V; ++q) acc[r][q] = t[0][r][q];
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int q = 0; q < V; ++q) acc[r][q] += t[0][r][q];
           }
+#pragma unroll
+          for (int j = 1; j < kLoadsInFlight; ++j)
+            if (j0 + j < nchild) {
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < V; ++q) acc[r][q] += t[j][r][q];
+            }
+        }
       }
       climbing = last && pcount > 1;
       if (last && pcount == 1) finish = true;

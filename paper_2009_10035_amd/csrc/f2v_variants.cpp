@@ -1,4 +1,6 @@
 // Lookup of the kernel instance for an embedding width.
+#include <cstdlib>
+
 #include "f2v_kernels.h"
 
 namespace f2v {
@@ -8,17 +10,42 @@ extern const Variant kVariants_bf16_v4[], kVariants_bf16_v2[];
 extern const int kNumVariants_f32_v4, kNumVariants_f32_v2, kNumVariants_f32_v1;
 extern const int kNumVariants_bf16_v4, kNumVariants_bf16_v2;
 
-// V = widest of 4, 2, 1 dividing d (bf16: 4 or 2); G = lanes per row, the
-// power of two covering d / V, at most 64; R = loads per lane (1, 2 or 4).
-const Variant* find_variant(int d, bool bf16) {
-  if (d <= 0) return nullptr;
-  int v;
-  if (d % 4 == 0) v = 4;
-  else if (d % 2 == 0) v = 2;
-  else if (!bf16) v = 1;
-  else return nullptr;
+// Fewest lanes per row (8).  Narrow rows still get several lanes (the extra
+// lanes hold no elements): fewer rows per wave means fewer rows of one wave
+// waiting on each other's dependencies, which matters more than lane use at
+// these widths (d = 2 layout epoch on 2M vertices: 20.3 ms with 1 lane per
+// row, 5.4 with 2, 3.0 with 4, 1.85 with 8, 2.2 with 16).  F2V_MIN_LANES (1..64,
+// power of two) overrides it.
+static int min_lanes() {
+  static const int value = [] {
+    int m = 8;
+    if (const char* env = std::getenv("F2V_MIN_LANES")) {
+      const int x = std::atoi(env);
+      if (x >= 1 && x <= 64 && (x & (x - 1)) == 0) m = x;
+    }
+    return m;
+  }();
+  return value;
+}
+
+// Preferred V: 8 bytes per lane and load (2 FP32 or 4 bf16 elements);
+// F2V_MAX_VEC = 1, 2 or 4 overrides it.  Measured on MI355X: Chung-Lu 1M,
+// d = 128 FP32: 9.4 ms per epoch with 64 lanes x float2 per row, 10.1 ms with
+// 32 lanes x float4 (fewer rows per wave wait on each other less); SBM 4M,
+// d = 128 bf16: 27.9 ms with 32 lanes x 4 bf16, 33.5 ms with 64 lanes x 2.
+static int max_vec(bool bf16) {
+  static const int forced = [] {
+    const char* env = std::getenv("F2V_MAX_VEC");
+    const int x = env ? std::atoi(env) : 0;
+    return (x == 1 || x == 2 || x == 4) ? x : 0;
+  }();
+  return forced ? forced : (bf16 ? 4 : 2);
+}
+
+static const Variant* lookup(int d, bool bf16, int v) {
+  if (d % v != 0 || (bf16 && v == 1)) return nullptr;
   const int lanes = d / v;
-  int g = 1;
+  int g = min_lanes();
   while (g < lanes && g < 64) g <<= 1;
   int r = (lanes + g - 1) / g;
   if (r == 3) r = 4;
@@ -36,6 +63,19 @@ const Variant* find_variant(int d, bool bf16) {
   }
   for (int i = 0; i < count; ++i)
     if (table[i].g == g && table[i].r == r) return &table[i];
+  return nullptr;
+}
+
+// Variant for width d: V = the widest vector up to max_vec(bf16) dividing d, else
+// the next wider one that has an instance (rows too wide for 64 lanes of V);
+// G = lanes per row, the power of two covering d / V (at least min_lanes(), at
+// most 64); R = loads per lane (1, 2 or 4).
+const Variant* find_variant(int d, bool bf16) {
+  if (d <= 0) return nullptr;
+  int v0 = max_vec(bf16);
+  while (v0 > 1 && d % v0 != 0) v0 >>= 1;
+  for (int v = v0; v <= 4; v <<= 1)
+    if (const Variant* x = lookup(d, bf16, v)) return x;
   return nullptr;
 }
 

@@ -70,7 +70,7 @@ def test_defaults_and_workspace():
     ("force", 2, "F2V_E_INVALID_ARG"), ("precision", 3, "F2V_E_INVALID_ARG"), ("lr0", 0.0, "F2V_E_INVALID_ARG"),
     ("lr0", float("nan"), "F2V_E_INVALID_ARG"), ("eps", 1.0, "F2V_E_INVALID_ARG"),
     ("eps", -0.1, "F2V_E_INVALID_ARG"), ("perm_mode", 2, "F2V_E_INVALID_ARG"),
-    ("schedule", 2, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
+    ("schedule", 3, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
 ])
 def test_validation(field, value, status):
     p = good()
