@@ -1,5 +1,6 @@
-"""Hash of the HIP sources, used to tell whether recorded hardware-counter
-measurements still describe the current kernels."""
+"""Hash of the sources of the update kernel (its template, the device helpers
+and argument structs it includes, and its instance files), used to tell
+whether recorded hardware-counter measurements still describe it."""
 import hashlib
 import os
 
@@ -9,7 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
+    names = [x for x in os.listdir(csrc)
+             if x in ("f2v_device.h", "f2v_kernels.h", "f2v_update_impl.h") or x.startswith("f2v_variants_")]
+    for name in sorted(names):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
