@@ -28,9 +28,9 @@ constexpr int64_t kMaxStatWaves = 16384;
 thread_local std::string g_error;
 
 struct Layout {
-  size_t zbuf1, bbuf0, bbuf1, perm, word, ucnt, uoff, dkey, order, negs, btot, breal, bstart, ngroups, units,
-      hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch, scan_total, loss_part, loss_out,
-      wave_stats, trace, ticket, total;
+  size_t zbuf1, bbuf0, bbuf1, perm, word, split_ids, pcol, ecnt, uoff, eoff, loff, dkey, order, negs, wreal,
+      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch,
+      scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket, total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
 
@@ -46,8 +46,10 @@ Layout layout_of(const f2v_params& p) {
   // a split row of degree deg > chunk has m = ceil(deg/chunk) < 2 deg / chunk
   // units, and its combining tree (fan-in >= 4) at most 1.6 m < 2 m nodes
   L.hub_slot_cap = 4 * ((p.nnz + chunk - 1) / chunk) + 8;
-  // tickets: one per unit, plus at most 63 padding tickets per batch
-  L.tmap_cap = n + p.nnz / chunk + L.nb * 63 + 64;
+  // tickets: one per whole row, at most deg/chunk + 2 per split row (fewer
+  // than 2 nnz/chunk over all split rows), and at most 63 padding tickets after
+  // each of a batch's two parts
+  L.tmap_cap = n + 2 * (p.nnz / chunk) + L.nb * 126 + 64;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   const bool bf16 = p.precision == F2V_BF16;
@@ -56,14 +58,23 @@ Layout layout_of(const f2v_params& p) {
   L.bbuf1 = take(bf16 ? size_t(n) * d * 2 : 0);
   L.perm = take(size_t(n) * 4);
   L.word = take(size_t(n) * 4);
-  L.ucnt = take(size_t(n) * 4);
+  L.split_ids = take(size_t(n) * 4);
+  L.pcol = take(size_t(p.nnz) * 4);
+  L.ecnt = take(size_t(n) * 4);
   L.uoff = take(size_t(n) * 4);
+  L.eoff = take(size_t(n) * 4);
+  L.loff = take(size_t(n) * 4);
   L.dkey = take(size_t(n) * 4);
   L.order = take(size_t(n) * 4);
   L.negs = take(size_t(L.nb) * (p.s > 0 ? p.s : 1) * 4);
-  L.btot = take(size_t(L.nb) * 4);
-  L.breal = take(size_t(L.nb) * 4);
+  L.wreal = take(size_t(L.nb) * 4);
+  L.ereal = take(size_t(L.nb) * 4);
+  L.lreal = take(size_t(L.nb) * 4);
+  L.epre = take(size_t(L.nb + 1) * 4);
+  L.areal = take(size_t(L.nb) * 4);
+  L.ebase = take(size_t(L.nb) * 4);
   L.bstart = take(size_t(L.nb + 1) * 4);
+  L.lstart = take(size_t(L.nb) * 4);
   L.ngroups = take(4);
   L.units = take(size_t(L.tmap_cap) * sizeof(f2v::Unit));
   L.hub_base = take(size_t(n) * 8);
@@ -73,6 +84,7 @@ Layout layout_of(const f2v_params& p) {
   L.csr_flag = take(4);
   L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
   L.scan_total = take(8);
+  L.split_total = take(8);
   L.loss_part = take(size_t(n) * 16);
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
@@ -147,6 +159,9 @@ struct f2v_ctx {
   bool record_events = true;  // off while a server captures the context's work into a graph
   int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
   int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
+  int32_t late_window = 8;    // batches whose neighbours a split row takes last (F2V_LATE_WINDOW)
+  int64_t nsplit = 0;         // rows of degree above chunk
+  int64_t hub_total = 0;      // combining-tree slots of all split rows
   std::string err;
 
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -287,6 +302,10 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (x >= 4 && x <= 64) c->fan_in = x;
   }
   if (const char* env = std::getenv("F2V_SORT")) c->sort = std::atoi(env) != 0;
+  if (const char* env = std::getenv("F2V_LATE_WINDOW")) {
+    const int x = std::atoi(env);
+    if (x >= 0 && x <= (1 << 20)) c->late_window = x;
+  }
   {
     // enough waves for about four groups each, at most the occupancy limit
     const int64_t groups = (L.tmap_cap + slots_of(c->var) - 1) / slots_of(c->var);
@@ -317,17 +336,23 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (hflag & 8u) m += " column index outside [0, n);";
     return bail(F2V_E_BAD_GRAPH, m);
   }
-  int64_t hub_total = 0;
+  int64_t hub_total = 0, nsplit = 0;
   if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
-      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, L.hub_slot_cap, s)) != hipSuccess)
+      (he = f2v::launch_split_ids(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.loss_part),
+                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.split_total),
+                                  c->at<int32_t>(L.split_ids), s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
   if (bf16 && (he = f2v::launch_to_bf16(d_z, c->bbuf[0], p->n * int64_t(p->d), s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("bf16 copy: ") + hipGetErrorString(he));
   if ((he = hipStreamSynchronize(s)) != hipSuccess ||
-      (he = hipMemcpy(&hub_total, c->at<int64_t>(L.scan_total), 8, hipMemcpyDeviceToHost)) != hipSuccess)
+      (he = hipMemcpy(&hub_total, c->at<int64_t>(L.scan_total), 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (he = hipMemcpy(&nsplit, c->at<int64_t>(L.split_total), 8, hipMemcpyDeviceToHost)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("init sync: ") + hipGetErrorString(he));
   if (hub_total > L.hub_slot_cap) return bail(F2V_E_INVALID_ARG, "split-row slots exceed the workspace bound");
+  if (nsplit < 0 || nsplit > p->n) return bail(F2V_E_INVALID_ARG, "split-row count out of range");
+  c->hub_total = hub_total;
+  c->nsplit = nsplit;
   *out = c;
   return F2V_OK;
 }
@@ -349,16 +374,27 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.order = c->at<int32_t>(L.order);
   sa.perm = c->at<int32_t>(L.perm);
   sa.word = c->at<uint32_t>(L.word);
-  sa.ucnt = c->at<int32_t>(L.ucnt);
+  sa.split_ids = c->at<int32_t>(L.split_ids);
+  sa.pcol = c->at<int32_t>(L.pcol);
+  sa.ecnt = c->at<int32_t>(L.ecnt);
   sa.uoff = c->at<int32_t>(L.uoff);
+  sa.eoff = c->at<int32_t>(L.eoff);
+  sa.loff = c->at<int32_t>(L.loff);
   sa.negs = c->at<int32_t>(L.negs);
-  sa.btot = c->at<int32_t>(L.btot);
-  sa.breal = c->at<int32_t>(L.breal);
+  sa.wreal = c->at<int32_t>(L.wreal);
+  sa.ereal = c->at<int32_t>(L.ereal);
+  sa.lreal = c->at<int32_t>(L.lreal);
+  sa.epre = c->at<int32_t>(L.epre);
+  sa.areal = c->at<int32_t>(L.areal);
+  sa.ebase = c->at<int32_t>(L.ebase);
   sa.bstart = c->at<int32_t>(L.bstart);
+  sa.lstart = c->at<int32_t>(L.lstart);
   sa.units = c->at<f2v::Unit>(L.units);
   sa.ngroups = c->at<int32_t>(L.ngroups);
   sa.ticket = c->at<uint32_t>(L.ticket);
   sa.n = p.n;
+  sa.nsplit = c->nsplit;
+  sa.late_window = c->late_window;
   sa.b = p.batch;
   sa.s = p.s;
   sa.nb = static_cast<int32_t>(L.nb);
@@ -372,9 +408,12 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;
   HIP_TRY(c, f2v::launch_setup(sa, s));
+  // tree counters and early-sum flags start every epoch at zero
+  if (c->hub_total > 0) HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, c->hub_total, s));
 
   EpochArgs A{};
   A.colidx = c->colidx;
+  A.pcol = sa.pcol;
   if (bf16) {
     A.zc = c->bbuf[c->cur];
     A.zn = c->bbuf[1 - c->cur];
@@ -388,6 +427,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.negs = sa.negs;
   A.units = sa.units;
   A.bstart = sa.bstart;
+  A.lstart = sa.lstart;
   A.ngroups = sa.ngroups;
   A.hub_base = c->at<int64_t>(L.hub_base);
   A.hub_cnt = c->at<uint32_t>(L.hub_cnt);
@@ -430,10 +470,15 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
     int grid = static_cast<int>((groups_hint + 3) / 4);
     if (grid < 1) grid = 1;
     if (grid > c->update_grid) grid = c->update_grid;
+    // per batch, its whole and early units, then (after the kernel boundary,
+    // which makes the early sums visible) its late units
     for (int64_t k = 0; k < L.nb; ++k) {
       A.strict_batch = static_cast<int32_t>(k);
-      void* args[] = {&A};
-      HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(grid), dim3(kBlock), args, 0, s));
+      for (int part = 0; part < (c->nsplit > 0 ? 2 : 1); ++part) {
+        A.strict_late = part;
+        void* args[] = {&A};
+        HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(grid), dim3(kBlock), args, 0, s));
+      }
     }
   }
   if (c->record_events) {

@@ -10,12 +10,45 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
-// One work unit of an epoch: chunk c (of nch) of vertex u's neighbour list,
-// len entries from CSR offset beg; u < 0 marks a padding ticket.
+// Kinds of work unit.  A row of degree at most `chunk` is one WHOLE unit (its
+// neighbours, the batch's negatives, the step).  A longer (split) row has its
+// neighbour list reordered each epoch into an early part and a late part: the
+// neighbours of the W = `late_window` batches just before its own come last.
+// The early part is cut into EARLY units of `chunk` entries whose partial sums
+// meet in a combining tree; the tree's root sum is stored and flagged.  The
+// LATE unit takes the late neighbours and the negatives, adds the early sum
+// and takes the step.
+//
+// Ticket order.  Each batch j has two parts, each padded to whole wave
+// groups: first the whole units of batch j and the early units of batch j + W
+// (of batches 0..W for j = 0), then the late units of batch j.  An early unit
+// of batch k reads nothing published after batch k - W, so it can run W
+// batches ahead and its tree is done long before the row's late neighbours
+// are.
+constexpr int32_t kUnitWhole = 1;
+constexpr int32_t kUnitEarly = 2;
+constexpr int32_t kUnitLate = 4;
+constexpr int32_t kUnitReordered = 8;   // list read from the reordered copy
+
+// One work unit of an epoch: len list entries from offset beg of vertex u's
+// row (in the CSR or its reordered copy).  Early units: chunk c of the nch
+// early units of the row; late unit: c = nch.  u < 0 marks a padding ticket.
 struct alignas(16) Unit {
   int64_t beg;
-  int32_t u, k, c, nch, len, pad;
+  int32_t u, k, c, nch, len, kind;
 };
+
+// Nodes of the combining tree over `units` leaves with fan-in `fan_in`: the
+// leaves, then ceil(count / fan_in) nodes per level up to a single root, which
+// is the last node.
+__host__ __device__ __forceinline__ int64_t tree_nodes(int64_t units, int32_t fan_in) {
+  int64_t total = units, count = units;
+  while (count > 1) {
+    count = (count + fan_in - 1) / fan_in;
+    total += count;
+  }
+  return total;
+}
 
 // Per-wave counters of the update kernel (diagnostics): kernel cycles, cycles
 // spent waiting for publications, cycles in split-row combines, work groups
@@ -26,6 +59,7 @@ enum WaveStat { kStatCycles = 0, kStatWaitCycles, kStatCombineCycles, kStatGroup
 // Everything one epoch's update kernel reads or writes.
 struct EpochArgs {
   const int32_t* colidx;    // [nnz]
+  const int32_t* pcol;      // [nnz] split rows' lists, early part then late part
   const void* zc;           // rows read this epoch: float or bf16 [n][d]
   void* zn;                 // rows written this epoch (same type) [n][d]
   float* master;            // BF16 form: FP32 master rows, updated in place
@@ -33,9 +67,11 @@ struct EpochArgs {
   const int32_t* negs;      // [nb][s] shared negatives of each batch
   const Unit* units;        // ticket -> work unit, in batch order
   const int32_t* bstart;    // [nb+1] first ticket of each batch (multiple of the slot count)
+  const int32_t* lstart;    // [nb] first ticket of each batch's late units (same)
   const int32_t* ngroups;   // device scalar: ticket groups this epoch
   const int64_t* hub_base;  // vertex -> first node of its combining tree (split rows)
-  uint32_t* hub_cnt;        // tree node -> arrival counter (accumulates over epochs)
+  uint32_t* hub_cnt;        // tree node -> arrival counter; a row's first slot flags its
+                            // early sum (all zero at the start of an epoch)
   float* hub_part;          // tree node -> partial sum [d]
   uint32_t* err;            // device error word (bit 0: a wait exceeded its bound)
   uint64_t* wave_stats;     // optional [waves][kWaveStats] cycle counters (nullptr: off)
@@ -45,31 +81,43 @@ struct EpochArgs {
   int32_t d, b, s, nb, force;
   float lr, eps;
   int32_t strict_batch;     // >= 0: process only this batch, no waits
+  int32_t strict_late;      // with strict_batch: 0 its whole and early units, 1 its late units
   uint32_t spin_limit;      // bound on polls of one dependency wait
   uint32_t* ticket;         // non-null: waves claim groups from this counter
   int32_t claim;            // groups per claim
   int32_t fan_in;           // fan-in of the combining tree of split rows
 };
 
-// Prologue of an epoch (random partition, negatives, work units).
+// Prologue of an epoch (random partition, negatives, split-row lists, work
+// units).
 struct SetupArgs {
   const int64_t* rowptr;
   const int32_t* colidx;
   int32_t* perm;            // position -> vertex
   uint32_t* word;           // vertex -> batch index (unpublished)
-  int32_t* ucnt;            // position -> work units of that row
-  int32_t* uoff;            // position -> unit offset inside its batch
+  const int32_t* split_ids; // [nsplit] vertices of degree above chunk
+  int32_t* pcol;            // [nnz] split rows' lists: early part, then late part
+  int32_t* ecnt;            // vertex -> length of the early part of its list (split rows)
+  int32_t* uoff;            // position -> offset of its whole unit among its batch's whole units
+  int32_t* eoff;            // position -> offset of its early units among its batch's early units
+  int32_t* loff;            // position -> offset of its late unit among its batch's late units
   int32_t* dkey;            // position -> latest earlier batch its row depends on (-1: none)
   int32_t* order;           // positions of each batch, sorted by dkey (then position)
   int32_t* negs;
-  int32_t* btot;            // [nb] unit count of each batch padded to the slot count
-  int32_t* breal;           // [nb] unit count of each batch
-  int32_t* bstart;          // [nb+1]
+  int32_t* wreal;           // [nb] whole units of each batch
+  int32_t* ereal;           // [nb] early units of each batch
+  int32_t* lreal;           // [nb] late units of each batch
+  int32_t* epre;            // [nb+1] exclusive prefix sums of ereal
+  int32_t* areal;           // [nb] units of each batch's first part
+  int32_t* ebase;           // [nb] first ticket of each batch's early units
+  int32_t* bstart;          // [nb+1] first ticket of each batch
+  int32_t* lstart;          // [nb] first ticket of each batch's second part
   Unit* units;
   int32_t* ngroups;
   uint32_t* ticket;         // claim counter of the dynamic schedule (reset here)
-  int64_t n;
+  int64_t n, nsplit;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave
+  int32_t late_window;      // batches before a split row's own whose neighbours go late
   uint64_t seed;
   uint32_t epoch;
   int32_t identity;
@@ -109,6 +157,10 @@ hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_
                             uint32_t* flag, hipStream_t st);
 hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int32_t fan_in,
                            int64_t* hub_base, int64_t* scratch, int64_t* total, hipStream_t st);
+// Vertices of degree above chunk, in increasing order, into split_ids; their
+// count into *count (device).  flags: [n] int64 scratch.
+hipError_t launch_split_ids(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* flags,
+                            int64_t* scratch, int64_t* count, int32_t* split_ids, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
 hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st);
 hipError_t launch_partition(int64_t n, uint64_t seed, uint32_t epoch, int identity, int32_t* perm,

@@ -31,8 +31,8 @@ __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
   return deg <= chunk ? 1 : static_cast<int32_t>((deg + chunk - 1) / chunk);
 }
 
-// K1: partition (position -> vertex, vertex -> batch word), units per
-// position, and the shared negatives of every batch.
+// K1: partition (position -> vertex, vertex -> batch word) and the shared
+// negatives of every batch.
 __global__ void k_setup_positions(SetupArgs A) {
   const Feistel f{A.seed, A.epoch, A.feistel_half, A.feistel_mask, A.n};
   const int64_t nneg = static_cast<int64_t>(A.nb) * A.s;
@@ -43,13 +43,55 @@ __global__ void k_setup_positions(SetupArgs A) {
       const int32_t v = A.identity ? static_cast<int32_t>(i) : feistel_permute(f, i);
       A.perm[i] = v;
       A.word[v] = static_cast<uint32_t>(i / A.b);
-      A.ucnt[i] = units_of(A.rowptr[v + 1] - A.rowptr[v], A.chunk);
     }
     if (i < nneg) {
       const uint32_t k = static_cast<uint32_t>(i / A.s), j = static_cast<uint32_t>(i % A.s);
       const uint4 x = philox(A.epoch, k, j, kTagNeg, A.seed);
       A.negs[i] = uniform_index(x.x, x.y, A.n);
     }
+  }
+}
+
+// Entries of a split row's list one wave looks at per round (8 per lane, so
+// that eight index and word loads per lane are in flight together).
+constexpr int kSplitTile = 8;
+
+// K1a: one wave per split row: reorder its list into pcol, the early part
+// (neighbours of later batches, of the row's own batch, or of batches more
+// than late_window before it) from the front in list order, the late part
+// from the back.  Both orders depend only on the list and the partition.
+__global__ void k_split_lists(SetupArgs A) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t i = wave; i < A.nsplit; i += nwaves) {
+    const int32_t u = A.split_ids[i];
+    const int32_t k = static_cast<int32_t>(A.word[u]);
+    const int64_t r0 = A.rowptr[u], r1 = A.rowptr[u + 1];
+    int64_t ne = 0, nl = 0;
+    for (int64_t base = r0; base < r1; base += 64 * kSplitTile) {
+      int32_t v[kSplitTile], kb[kSplitTile];
+#pragma unroll
+      for (int j = 0; j < kSplitTile; ++j) {
+        const int64_t e = base + j * 64 + lane;
+        v[j] = e < r1 ? A.colidx[e] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kSplitTile; ++j) kb[j] = v[j] >= 0 ? static_cast<int32_t>(A.word[v[j]]) : 0;
+#pragma unroll
+      for (int j = 0; j < kSplitTile; ++j) {
+        const bool valid = v[j] >= 0;
+        const bool late = valid && kb[j] < k && kb[j] >= k - A.late_window;
+        const bool early = valid && !late;
+        const uint64_t me = __ballot(early), ml = __ballot(late);
+        if (early) A.pcol[r0 + ne + __popcll(me & below)] = v[j];
+        if (late) A.pcol[r1 - 1 - (nl + __popcll(ml & below))] = v[j];
+        ne += __popcll(me);
+        nl += __popcll(ml);
+      }
+    }
+    if (lane == 0) A.ecnt[u] = static_cast<int32_t>(ne);
   }
 }
 
@@ -80,11 +122,46 @@ __global__ void k_readiness(SetupArgs A, const int32_t* colidx) {
 // Batches larger than this keep position order (no readiness sort).
 constexpr int kSortMax = 2048;
 
+// Work units of the row at a position: whole units in the low 32 bits, late
+// units in the high 32 bits (one of the two is 1, the other 0).
+__device__ __forceinline__ int64_t whole_late(const SetupArgs& A, int32_t u) {
+  const int64_t deg = A.rowptr[u + 1] - A.rowptr[u];
+  return deg <= A.chunk ? 1 : (int64_t{1} << 32);
+}
+
+// Early units of the row of vertex u (split rows only).
+__device__ __forceinline__ int64_t early_units(const SetupArgs& A, int32_t u) {
+  const int64_t deg = A.rowptr[u + 1] - A.rowptr[u];
+  if (deg <= A.chunk) return 0;
+  return (static_cast<int64_t>(A.ecnt[u]) + A.chunk - 1) / A.chunk;
+}
+
+// Block-wide exclusive scan of c over the positions lo..hi (in `order`),
+// writing the offsets through `put` and returning the total.
+template <typename Count, typename Put>
+__device__ int64_t scan_positions(const SetupArgs& A, int64_t lo, int64_t hi, int64_t* lds,
+                                  int64_t* tile_total, Count count, Put put) {
+  int64_t carry = 0;
+  for (int64_t base = lo; base < hi; base += blockDim.x) {
+    const int64_t r = base + threadIdx.x;
+    const int32_t p = r < hi ? A.order[r] : 0;
+    const int64_t c = r < hi ? count(A.perm[p]) : 0;
+    const int64_t inc = block_inclusive_scan(c, lds);
+    if (r < hi) put(p, carry + inc - c);
+    // the tile total is the last thread's inclusive value
+    if (threadIdx.x == blockDim.x - 1) *tile_total = inc;
+    __syncthreads();
+    carry += *tile_total;
+    __syncthreads();
+  }
+  return carry;
+}
+
 // K2: one block per batch: order the batch's positions by readiness (rows
-// whose dependencies are older first; ties by position), then the unit
-// offsets in that order, and the batch's unit count padded to a multiple of
-// the lane groups per wave.  Rows of one batch are independent, so the order
-// inside a batch changes no result.
+// whose dependencies are older first; ties by position), then in that order
+// the offsets of each row's whole, early and late units among the batch's
+// units of that kind, and the batch's counts of each kind.  Rows of one batch
+// are independent, so the order inside a batch changes no result.
 __global__ void k_batch_units(SetupArgs A) {
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
@@ -110,35 +187,70 @@ __global__ void k_batch_units(SetupArgs A) {
   }
   __syncthreads();
   __threadfence_block();
+  // whole and late counts in one scan: the halves never carry into each other
+  const int64_t wl = scan_positions(
+      A, lo, hi, lds, &tile_total, [&](int32_t u) { return whole_late(A, u); },
+      [&](int32_t p, int64_t ex) {
+        A.uoff[p] = static_cast<int32_t>(ex & 0xffffffffll);
+        A.loff[p] = static_cast<int32_t>(ex >> 32);
+      });
+  const int64_t ne = scan_positions(
+      A, lo, hi, lds, &tile_total, [&](int32_t u) { return early_units(A, u); },
+      [&](int32_t p, int64_t ex) { A.eoff[p] = static_cast<int32_t>(ex); });
+  if (threadIdx.x == 0) {
+    A.wreal[k] = static_cast<int32_t>(wl & 0xffffffffll);
+    A.lreal[k] = static_cast<int32_t>(wl >> 32);
+    A.ereal[k] = static_cast<int32_t>(ne);
+  }
+}
+
+// Batch whose first part holds the early units of batch k.
+__device__ __forceinline__ int32_t early_home(int32_t k, int32_t window) {
+  return k - window > 0 ? k - window : 0;
+}
+
+// K3: one block: per batch, the units of its first part (its whole units
+// and the early units it holds), the first ticket of the batch, of its second
+// part and of its early units, and the group count.
+__global__ void k_batch_starts(SetupArgs A) {
+  __shared__ int64_t lds[kScanThreads];
+  __shared__ int64_t tile_total;
+  // exclusive prefix of the early counts
   int64_t carry = 0;
-  for (int64_t base = lo; base < hi; base += blockDim.x) {
-    const int64_t r = base + threadIdx.x;
-    const int32_t p = r < hi ? A.order[r] : 0;
-    const int64_t c = r < hi ? A.ucnt[p] : 0;
+  for (int64_t base = 0; base < A.nb; base += blockDim.x) {
+    const int64_t k = base + threadIdx.x;
+    const int64_t c = k < A.nb ? A.ereal[k] : 0;
     const int64_t inc = block_inclusive_scan(c, lds);
-    if (r < hi) A.uoff[p] = static_cast<int32_t>(carry + inc - c);
-    // the tile total is the last thread's inclusive value
+    if (k < A.nb) A.epre[k] = static_cast<int32_t>(carry + inc - c);
     if (threadIdx.x == blockDim.x - 1) tile_total = inc;
     __syncthreads();
     carry += tile_total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    A.breal[k] = static_cast<int32_t>(carry);
-    A.btot[k] = static_cast<int32_t>((carry + A.slots - 1) / A.slots * A.slots);
-  }
-}
-
-// K3: one block: first ticket of every batch, and the group count.
-__global__ void k_batch_starts(SetupArgs A) {
-  __shared__ int64_t lds[kScanThreads];
-  __shared__ int64_t tile_total;
-  int64_t carry = 0;
+  if (threadIdx.x == 0) A.epre[A.nb] = static_cast<int32_t>(carry);
+  __syncthreads();
+  __threadfence_block();
+  // the first part of batch j holds the early units of batch j + W (j > 0)
+  // or of batches 0..W (j = 0)
+  const int64_t w = A.late_window;
+  carry = 0;
   for (int64_t base = 0; base < A.nb; base += blockDim.x) {
-    const int64_t k = base + threadIdx.x;
-    const int64_t c = k < A.nb ? A.btot[k] : 0;
+    const int64_t j = base + threadIdx.x;
+    int64_t c = 0, first = 0;
+    if (j < A.nb) {
+      int64_t held;
+      if (j == 0) held = A.epre[w + 1 < A.nb ? w + 1 : A.nb];
+      else held = j + w < A.nb ? A.ereal[j + w] : 0;
+      first = A.wreal[j] + held;
+      A.areal[j] = static_cast<int32_t>(first);
+      first = (first + A.slots - 1) / A.slots * A.slots;
+      c = first + (A.lreal[j] + A.slots - 1) / A.slots * A.slots;
+    }
     const int64_t inc = block_inclusive_scan(c, lds);
-    if (k < A.nb) A.bstart[k] = static_cast<int32_t>(carry + inc - c);
+    if (j < A.nb) {
+      A.bstart[j] = static_cast<int32_t>(carry + inc - c);
+      A.lstart[j] = static_cast<int32_t>(carry + inc - c + first);
+    }
     if (threadIdx.x == blockDim.x - 1) tile_total = inc;
     __syncthreads();
     carry += tile_total;
@@ -149,40 +261,65 @@ __global__ void k_batch_starts(SetupArgs A) {
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
     *A.ticket = 0u;
   }
+  __syncthreads();
+  __threadfence_block();
+  for (int64_t k = threadIdx.x; k < A.nb; k += blockDim.x) {
+    const int32_t h = early_home(static_cast<int32_t>(k), A.late_window);
+    // early units of batches sharing batch 0's first part follow each other
+    A.ebase[k] = A.bstart[h] + A.wreal[h] + (h == 0 ? A.epre[k] : 0);
+  }
 }
 
 // K4: work units in ticket order.  Threads [0, n) write the units of one
-// position; threads [n, n + nb*slots) mark the padding tickets at the end of
-// each batch.
+// position; threads [n, n + 2*nb*slots) mark the padding tickets at the end of
+// each batch's two parts.
 __global__ void k_tickets(SetupArgs A) {
-  const int64_t pad_threads = static_cast<int64_t>(A.nb) * A.slots;
+  const int64_t pad_threads = 2 * static_cast<int64_t>(A.nb) * A.slots;
   const int64_t total = A.n + pad_threads;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     if (i < A.n) {
       const int32_t k = static_cast<int32_t>(i / A.b);
-      const int64_t t0 = static_cast<int64_t>(A.bstart[k]) + A.uoff[i];
       const int32_t u = A.perm[i];
-      const int32_t cnt = A.ucnt[i];
       const int64_t r0 = A.rowptr[u], deg = A.rowptr[u + 1] - r0;
-      for (int32_t c = 0; c < cnt; ++c) {
-        Unit w;
-        w.beg = r0 + static_cast<int64_t>(c) * A.chunk;
-        w.u = u;
-        w.k = k;
-        w.c = c;
-        w.nch = cnt;
-        const int64_t rest = deg - static_cast<int64_t>(c) * A.chunk;
-        w.len = static_cast<int32_t>(rest < A.chunk ? rest : A.chunk);
-        w.pad = 0;
-        A.units[t0 + c] = w;
+      Unit w;
+      w.u = u;
+      w.k = k;
+      if (deg <= A.chunk) {
+        w.beg = r0;
+        w.c = 0;
+        w.nch = 0;
+        w.len = static_cast<int32_t>(deg);
+        w.kind = kUnitWhole;
+        A.units[static_cast<int64_t>(A.bstart[k]) + A.uoff[i]] = w;
+      } else {
+        const int32_t early = A.ecnt[u];
+        const int32_t m = (early + A.chunk - 1) / A.chunk;
+        const int64_t t0 = static_cast<int64_t>(A.ebase[k]) + A.eoff[i];
+        w.nch = m;
+        w.kind = kUnitEarly | kUnitReordered;
+        for (int32_t c = 0; c < m; ++c) {
+          w.beg = r0 + static_cast<int64_t>(c) * A.chunk;
+          w.c = c;
+          const int32_t rest = early - c * A.chunk;
+          w.len = rest < A.chunk ? rest : A.chunk;
+          A.units[t0 + c] = w;
+        }
+        w.beg = r0 + early;
+        w.c = m;
+        w.len = static_cast<int32_t>(deg - early);
+        w.kind = kUnitLate | kUnitReordered;
+        A.units[static_cast<int64_t>(A.lstart[k]) + A.loff[i]] = w;
       }
     } else {
       const int64_t j = i - A.n;
-      const int32_t k = static_cast<int32_t>(j / A.slots);
-      const int32_t q = static_cast<int32_t>(j % A.slots);
-      const int64_t t = static_cast<int64_t>(A.bstart[k]) + A.breal[k] + q;
-      if (t < A.bstart[k + 1]) {
+      const int32_t k = static_cast<int32_t>(j / (2 * A.slots));
+      const int32_t q = static_cast<int32_t>(j % (2 * A.slots));
+      // the first slots threads pad the first part, the others the second
+      const int64_t t = q < A.slots ? static_cast<int64_t>(A.bstart[k]) + A.areal[k] + q
+                                    : static_cast<int64_t>(A.lstart[k]) + A.lreal[k] + (q - A.slots);
+      const int64_t end = q < A.slots ? A.lstart[k] : A.bstart[k + 1];
+      if (t < end) {
         Unit w{};
         w.u = -1;
         A.units[t] = w;
@@ -213,17 +350,6 @@ __global__ void k_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_
     const int32_t c = colidx[e];
     if (c < 0 || c >= n) atomicOr(flag, 8u);
   }
-}
-
-// Nodes of the combining tree of a split row with `units` units: the units,
-// then ceil(count / fan_in) nodes per level up to a single root.
-__device__ __forceinline__ int64_t tree_nodes(int64_t units, int32_t fan_in) {
-  int64_t total = units, count = units;
-  while (count > 1) {
-    count = (count + fan_in - 1) / fan_in;
-    total += count;
-  }
-  return total;
 }
 
 // Split-row slots (partial sums and arrival counters): per vertex, the nodes
@@ -267,6 +393,20 @@ __global__ void k_scan_top(int64_t* block_sums, int64_t nblocks, int64_t* total)
 __global__ void k_scan_add(int64_t* data, const int64_t* block_sums, int64_t n) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i < n) data[i] += block_sums[blockIdx.x];
+}
+
+// Split-row list at init: flag, exclusive scan, scatter.
+__global__ void k_split_flags(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* flags) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    flags[i] = rowptr[i + 1] - rowptr[i] > chunk ? 1 : 0;
+}
+
+__global__ void k_split_scatter(const int64_t* rowptr, int64_t n, int32_t chunk, const int64_t* slot,
+                                int32_t* split_ids) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    if (rowptr[i + 1] - rowptr[i] > chunk) split_ids[slot[i]] = static_cast<int32_t>(i);
 }
 
 __global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t count) {
@@ -357,10 +497,12 @@ int grid_for(int64_t work, int threads) {
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(a.n > nneg ? a.n : nneg, 256)), dim3(256), 0, st, a);
+  if (a.nsplit > 0) hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
   if (a.sort) hipLaunchKernelGGL(k_readiness, dim3((a.n * 16 + 255) / 256), dim3(256), 0, st, a, a.colidx);
   hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
   hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);
-  hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + 2 * static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0,
+                     st, a);
   return hipGetLastError();
 }
 
@@ -384,6 +526,18 @@ hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int3
   hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanThreads), 0, st, hub_base, scratch, n);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scratch, nblocks, total);
   hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanThreads), 0, st, hub_base, scratch, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_ids(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* flags,
+                            int64_t* scratch, int64_t* count, int32_t* split_ids, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, rowptr, n, chunk, flags);
+  const int64_t nblocks = (n + kScanThreads - 1) / kScanThreads;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(kScanThreads), 0, st, flags, scratch, n);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scratch, nblocks, count);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(kScanThreads), 0, st, flags, scratch, n);
+  hipLaunchKernelGGL(k_split_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, rowptr, n, chunk, flags,
+                     split_ids);
   return hipGetLastError();
 }
 

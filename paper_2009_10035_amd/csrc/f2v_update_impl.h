@@ -3,20 +3,24 @@
 //
 // Work decomposition.  A lane group of G lanes owns one vertex row u (each lane
 // holds R vectors of V consecutive elements), so a wave processes 64/G rows at
-// once.  A work unit is one row's neighbour list, or for rows of degree above
-// `chunk` one chunk of it; the first unit of a row also carries the batch's
-// shared negatives.  Units of a split row store partial sums and the last one
-// to arrive adds all partials in unit order, then takes the step, so the result
-// does not depend on which unit finishes last.
+// once.  A row of degree at most `chunk` is one work unit.  A longer row is
+// split: its early units (chunks of the neighbours that are ready long before
+// the row's turn) store partial sums that meet in a combining tree, and its
+// late unit (the neighbours of the last few batches and the shared negatives)
+// adds the tree's root sum and takes the step.  Every sum's association is
+// fixed by the lists and the tree, so the result does not depend on timing.
 //
 // Synchronous minibatch semantics on a device that overlaps batches.  The
 // epoch reads rows from `zc` (the state at the start of the epoch) and writes
 // every updated row once into `zn`.  A unit of batch k reading vertex x takes
 // zn[x] if x belongs to an earlier batch (after waiting until x's word shows it
 // published) and zc[x] otherwise, so every read sees exactly the state the
-// sequential algorithm has at the start of batch k.  Units are visited in
-// batch order, a wave's lane groups always belong to one batch and waits are
-// only on earlier batches, so a co-resident grid always makes progress.
+// sequential algorithm has at the start of batch k.  Tickets are in batch
+// order, and inside a batch all whole and early units come before the late
+// units, in separate wave groups.  A unit waits only on units of earlier
+// batches, and a late unit also on early units of its own batch, all at lower
+// tickets; waves take their tickets in increasing order, so in a co-resident
+// grid the lowest unfinished ticket can always proceed.
 #pragma once
 #include "f2v_device.h"
 #include "f2v_kernels.h"
@@ -44,10 +48,12 @@ struct Unroll {
   static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : 8);
 };
 
-// Diagnostic counters of one wave (kept in registers, written at kernel end).
+// Diagnostic counters of one wave, kept in LDS (not registers, which the
+// update loop needs) and written out at kernel end.  Every lane applies the
+// same update, so the wave's lanes agree on every value.
 struct WaveCounters {
-  uint64_t wait = 0, combine = 0, publish = 0, groups = 0, polls = 0, waits = 0;
-  uint64_t last_wait_end = 0;  // wall clock at the end of the unit's last wait
+  uint64_t wait, combine, publish, groups, polls, waits;
+  uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
@@ -145,8 +151,12 @@ constexpr uint32_t kEntPending = 1u << 30;
 constexpr uint32_t kEntNext = 1u << 31;
 constexpr uint32_t kEntNone = kEntVertex;  // no entry (vertex ids stay below it)
 
-// Partial rows a combining-tree node loads at a time.
-constexpr int kLoadsInFlight = 8;
+// Partial rows a combining-tree node loads at a time (the trees are off the
+// critical path; few loads in flight keep the register budget low).
+template <int R, int V>
+struct TreeLoads {
+  static constexpr int value = 4;
+};
 
 // Forces between the group's row `a` and the entries of its unit's list:
 // `len` CSR neighbours from `nbr` (attraction), then `nneg` shared negatives
@@ -281,14 +291,56 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
   }
 }
 
-// One work unit (chunk w.c of vertex w.u's list in batch w.k).
+// Wait until the flag word at `flag` (per lane group; nullptr: none) is set.
+// Bounded like wait_published.
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
+  bool pend = flag != nullptr;
+  if (!__any(pend)) return;
+  const uint64_t t0 = A.wave_stats ? clock64() : 0;
+  uint32_t polls = 0;
+  while (true) {
+    if (pend) pend = ld_coherent_u32(flag) == 0u;
+    if (!__any(pend)) break;
+    ++polls;
+    if (polls >= A.spin_limit) {
+      if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+      break;
+    }
+    if ((polls & 255u) == 0 && ld_coherent_u32(A.err) != 0) break;
+    if (polls < 8) __builtin_amdgcn_s_sleep(1);
+    else if (polls < 32) __builtin_amdgcn_s_sleep(4);
+    else __builtin_amdgcn_s_sleep(16);
+  }
+  compiler_fence();
+  if (A.wave_stats) {
+    wc.wait += clock64() - t0;
+    wc.polls += polls;
+    wc.waits += 1;
+  }
+}
+
+// Store the lane's part of a partial-sum row.
+template <int G, int V, int R>
+__device__ __forceinline__ void store_partial(float* row, int d, int l, const float (&acc)[R][V]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e0 = (r * G + l) * V;
+    if (e0 < d) store_coherent_f32<V>(row + e0, acc[r]);
+  }
+}
+
+// One work unit (see the unit kinds): accumulate its list, then either take
+// the step of Eq. 10 and publish the row (whole and late units) or add the
+// partial sum into the row's combining tree (early units).
 template <int G, int V, int R, bool BF16>
 __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
                                              bool wait, uint32_t* order, WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
   const bool active = w.u >= 0;
   const int32_t u = active ? w.u : 0;
-  wc.last_wait_end = 0;
+  const bool early = active && (w.kind & kUnitEarly) != 0;
+  const bool late = active && (w.kind & kUnitLate) != 0;
+  if (A.trace) wc.last_wait_end = 0;
   float a[R][V], acc[R][V];
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -302,36 +354,44 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 #pragma unroll
       for (int i = 0; i < V; ++i) a[r][i] = 0.0f;
   }
-
-  // attraction over the unit's neighbours, then (first unit of the row)
-  // repulsion from the batch's shared negatives: Algorithm 2's two loops
-  const int32_t nneg = (active && w.c == 0) ? A.s : 0;
-  accumulate_unit<G, V, R, BF16>(A, active, A.colidx + w.beg, w.len,
-                                 A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s, nneg,
-                                 w.k, wait, l, slot, order, a, acc, wc);
-
-  // split rows: the units' partial sums are added up a tree of fan-in
-  // A.fan_in (levels L = 0 .. T, level 0 = the units, one node at level T);
-  // the last child to arrive at a node sums the node's children in index
-  // order and climbs, so the sum's association is fixed by the tree alone
-  bool finish = active;
-  const bool split = active && w.nch > 1;
-  if (__any(split)) {
-    const uint64_t tc = A.wave_stats ? clock64() : 0;
-    const int64_t base = split ? A.hub_base[u] : 0;
-    bool climbing = split;
-    finish = !split && active;
-    int32_t node = w.c, count = w.nch, off = 0;  // current node and its level's size/offset
-    if (split) {
-      float* part = A.hub_part + (base + node) * A.d;
+  // late unit: start from the early part's sum (the root of its tree), once
+  // its flag is set
+  const bool has_early = late && w.nch > 0;
+  if (__any(has_early)) {
+    const int64_t base = has_early ? A.hub_base[u] : 0;
+    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, wc);
+    if (has_early) {
+      const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e0 = (r * G + l) * V;
-        if (e0 < A.d) store_coherent_f32<V>(part + e0, acc[r]);
+        if (e0 < A.d) load_coherent<V, false>(root + e0, acc[r]);
       }
     }
+  }
+
+  // attraction over the unit's neighbours, then (whole and late units)
+  // repulsion from the batch's shared negatives: Algorithm 2's two loops
+  const int32_t nneg = (active && !early) ? A.s : 0;
+  const int32_t* list = (w.kind & kUnitReordered) ? A.pcol : A.colidx;
+  accumulate_unit<G, V, R, BF16>(A, active, list + (active ? w.beg : 0), w.len,
+                                 A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s, nneg,
+                                 w.k, wait, l, slot, order, a, acc, wc);
+
+  // early units: the partial sums are added up a tree of fan-in A.fan_in
+  // (level 0 = the units, one root); the last child to arrive at a node sums
+  // the node's children in index order and climbs, so the sum's association
+  // is fixed by the tree alone.  The root's sum is stored in the root's slot
+  // and the row's flag (its first counter slot, which no node uses) is set.
+  if (__any(early)) {
+    const uint64_t tc = A.wave_stats ? clock64() : 0;
+    const int64_t base = early ? A.hub_base[u] : 0;
+    bool climbing = early && w.nch > 1;
+    bool flag_it = early && w.nch == 1;
+    if (early) store_partial<G, V, R>(A.hub_part + (base + w.c) * A.d, A.d, l, acc);
     drain_memory();
     const int32_t fan = A.fan_in;
+    int32_t node = w.c, count = w.nch, off = 0;  // current node and its level's size/offset
     while (__any(climbing)) {
       const int32_t parent = node / fan;
       const int32_t pcount = (count + fan - 1) / fan;
@@ -344,10 +404,11 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
                                      __HIP_MEMORY_SCOPE_AGENT);
       old = __shfl(old, slot * G, 64);
       compiler_fence();
-      const bool last = climbing && (old + 1u) % static_cast<uint32_t>(nchild) == 0u;
+      const bool last = climbing && old + 1u == static_cast<uint32_t>(nchild);
       if (last) {
         // children in index order, kLoadsInFlight partial rows at a time
         const float* kids = A.hub_part + (base + off + first) * A.d;
+        constexpr int kLoadsInFlight = TreeLoads<R, V>::value;
         for (int j0 = 0; j0 < nchild; j0 += kLoadsInFlight) {
           float t[kLoadsInFlight][R][V];
 #pragma unroll
@@ -382,26 +443,21 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
                 for (int q = 0; q < V; ++q) acc[r][q] += t[j][r][q];
             }
         }
+        store_partial<G, V, R>(A.hub_part + (base + poff + parent) * A.d, A.d, l, acc);
       }
       climbing = last && pcount > 1;
-      if (last && pcount == 1) finish = true;
-      if (climbing) {
-        float* part = A.hub_part + (base + poff + parent) * A.d;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int e0 = (r * G + l) * V;
-          if (e0 < A.d) store_coherent_f32<V>(part + e0, acc[r]);
-        }
-      }
+      if (last && pcount == 1) flag_it = true;
       drain_memory();
       node = parent;
       count = pcount;
       off = poff;
     }
+    if (flag_it && l == 0) st_coherent_u32(A.hub_cnt + base, 1u);
     if (A.wave_stats) wc.combine += clock64() - tc;
   }
 
   // the step of Eq. 10 and its publication
+  const bool finish = active && !early;
   const uint64_t tp = A.wave_stats ? clock64() : 0;
   if (finish) {
 #pragma unroll
@@ -444,21 +500,24 @@ __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
   __shared__ uint32_t order_lds[4][64 * ListShape<G>::kIdxPerLane];
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // wave-uniform (so that with one row per wave the unit records are scalar loads)
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   uint32_t* order = order_lds[threadIdx.x >> 6];
   int gbeg, gend;
   bool wait;
   if (A.strict_batch >= 0) {
-    gbeg = A.bstart[A.strict_batch] / S;
-    gend = A.bstart[A.strict_batch + 1] / S;
+    gbeg = (A.strict_late ? A.lstart[A.strict_batch] : A.bstart[A.strict_batch]) / S;
+    gend = (A.strict_late ? A.bstart[A.strict_batch + 1] : A.lstart[A.strict_batch]) / S;
     wait = false;
   } else {
     gbeg = 0;
     gend = *A.ngroups;
     wait = true;
   }
-  WaveCounters wc;
+  __shared__ WaveCounters wc_lds[4];
+  WaveCounters& wc = wc_lds[threadIdx.x >> 6];
+  if (A.wave_stats || A.trace) wc = WaveCounters{0, 0, 0, 0, 0, 0, 0};
   const uint64_t t_start = A.wave_stats ? clock64() : 0;
   if (A.ticket) {
     // dynamic: claim `claim` consecutive groups at a time, in batch order

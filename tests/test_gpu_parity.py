@@ -85,6 +85,27 @@ def test_dataflow_equals_strict_and_oracle(maker, chunk, d, force):
     assert rel_fro(a[0], ref) <= TOL
 
 
+@pytest.mark.parametrize("window", [0, 1, 8, 1 << 20])
+@pytest.mark.parametrize("fan_in", [4, 8])
+def test_split_rows_late_window(window, fan_in, monkeypatch):
+    """Split rows under every early/late division: no late neighbours (window
+    0), a few, and all neighbours of earlier batches late (so some rows have
+    no early units and others one or many, with trees of several levels).
+    The three schedules agree bit for bit, the oracle within the tolerance."""
+    monkeypatch.setenv("F2V_LATE_WINDOW", str(window))
+    monkeypatch.setenv("F2V_FAN_IN", str(fan_in))
+    g = gg.chung_lu(20000, 2.1, 20.0, 3)
+    p = dict(d=32, batch=96, s=5, force="sigmoid", lr0=0.02, seed=5, chunk=8)
+    Z0 = gg.init_embedding(g.n, p["d"], 3)
+    a = gpu_run(g, Z0, p, 2, schedule="dataflow")
+    b = gpu_run(g, Z0, p, 2, schedule="strict")
+    c = gpu_run(g, Z0, p, 2, schedule="dynamic")
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    ref = oracle.epoch(g, Z0, 0, oracle_params(p))
+    assert rel_fro(a[0], ref) <= TOL
+
+
 def test_run_twice_and_resume_bitwise():
     g = gg.chung_lu(30000, 2.1, 20.0, 5)
     p = dict(d=64, batch=384, s=5, force="sigmoid", lr0=0.02, seed=1)
