@@ -250,6 +250,43 @@ __device__ __forceinline__ float group_sum(float x) {
   return x;
 }
 
+// Value of lane `src` of the caller's row of 16 lanes (DPP row broadcast).
+template <int kSrc>
+__device__ __forceinline__ float row_broadcast(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150 + kSrc,
+                                                             0xF, 0xF, false));
+}
+// x of this lane plus x of the lane whose index differs by `kCtrl`'s pattern,
+// where the partner's value is `send` (selected per lane).
+template <int kCtrl>
+__device__ __forceinline__ float dpp_add_from(float keep, float send) {
+  return keep + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), kCtrl,
+                                                                    0xF, 0xF, false));
+}
+
+// Sums over the G lanes of a group (G >= 16) of eight per-lane partials at
+// once.  Three exchange levels inside each 8-lane segment halve the values a
+// lane holds (partners: the half-row mirror, xor 2, xor 1), leaving lane l with
+// the segment's sum for value l % 8; the remaining levels (xor 8, 16, 32) add
+// the segments.  Every lane of a group that holds value j has the same bits.
+// Must be called with all 64 lanes active.
+template <int G>
+__device__ __forceinline__ float group_sum8_scatter(const float (&p)[8]) {
+  static_assert(G >= 16, "needs rows of 16 lanes");
+  const int l = threadIdx.x & 63;
+  const bool b2 = (l & 4) != 0, b1 = (l & 2) != 0, b0 = (l & 1) != 0;
+  float n[4], m[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) n[j] = dpp_add_from<0x141>(b2 ? p[j + 4] : p[j], b2 ? p[j] : p[j + 4]);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) m[j] = dpp_add_from<0x4E>(b1 ? n[j + 2] : n[j], b1 ? n[j] : n[j + 2]);
+  float r = dpp_add_from<0xB1>(b0 ? m[1] : m[0], b0 ? m[0] : m[1]);
+  r = dpp_add_from<0x128>(r, r);   // row_ror:8 within 16 lanes: xor 8
+  if constexpr (G >= 32) r += __shfl_xor(r, 16, 64);
+  if constexpr (G == 64) r += __shfl_xor(r, 32, 64);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Per-pair forces: gradient of the per-vertex loss with respect to z_u.
 // `dotq` is z_u . z_v (sigmoid) or |z_u - z_v|^2 (Student-t), summed over the

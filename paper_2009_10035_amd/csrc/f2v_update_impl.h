@@ -69,6 +69,7 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
   if (!__any(any)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
   uint32_t polls = 0;
+#pragma clang loop unroll(disable)
   while (true) {
     // each lane polls only its first pending entry: one load per lane and
     // round keeps the poll traffic small while many waves wait
@@ -158,24 +159,96 @@ struct TreeLoads {
   static constexpr int value = 4;
 };
 
+// One batch of up to U entries (`cnt` left from `ent`, in LDS) of one region
+// of a step: rows of the epoch-start buffer (kNext false: plain loads, no
+// wait) or of earlier batches (kNext: awaited, device-scope loads).  Adds each
+// entry's force on the group's row `a` into acc, in entry order.
+template <int G, int V, int R, bool BF16, int kForce, bool kNext, int U>
+__device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint32_t* ent, int cnt, bool wait,
+                                                 int l, const float (&a)[R][V], float (&acc)[R][V],
+                                                 WaveCounters& wc) {
+  using T = typename Elem<BF16>::T;
+  const T* src = static_cast<const T*>(kNext ? A.zn : A.zc);
+  int32_t vid[U];
+  bool pend[U], rep[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const uint32_t e = q < cnt ? ent[q] : kEntNone;
+    vid[q] = (e & kEntVertex) == kEntNone ? -1 : static_cast<int32_t>(e & kEntVertex);
+    pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
+    rep[q] = (e & kEntRepulsive) != 0u;
+  }
+  if (kNext && wait) wait_published<U>(A, vid, pend, wc);
+  float y[U][R][V];
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    if (vid[q] >= 0) {
+      load_row<G, V, R, BF16>(src, vid[q], A.d, l, kNext, y[q]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+    }
+  }
+  float dq[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) dq[q] = pair_partial<R, V>(kForce, a, y[q]);
+  float cq[U];
+  if constexpr (G >= 16 && U == 8) {
+    // the eight sums at once; lane l computes the coefficient of row l % 8
+    // and every lane reads the eight coefficients back
+    uint32_t repmask = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
+    const float dl = group_sum8_scatter<G>(dq);
+    const int row = static_cast<int>(threadIdx.x & 7);
+    const float cl = ((repmask >> row) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+    cq[0] = row_broadcast<0>(cl); cq[1] = row_broadcast<1>(cl);
+    cq[2] = row_broadcast<2>(cl); cq[3] = row_broadcast<3>(cl);
+    cq[4] = row_broadcast<4>(cl); cq[5] = row_broadcast<5>(cl);
+    cq[6] = row_broadcast<6>(cl); cq[7] = row_broadcast<7>(cl);
+  } else {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const float t = group_sum<G>(dq[q]);
+      cq[q] = rep[q] ? repulse_coef(kForce, t, A.eps) : attract_coef(kForce, t);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    if (vid[q] >= 0) {
+      const float c = cq[q];
+      if constexpr (kForce == kSigmoid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, y[q][r][i], acc[r][i]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, a[r][i] - y[q][r][i], acc[r][i]);
+      }
+    }
+  }
+}
+
 // Forces between the group's row `a` and the entries of its unit's list:
 // `len` CSR neighbours from `nbr` (attraction), then `nneg` shared negatives
 // from `neg` (repulsion).  The list is taken in steps; inside a step the
 // entries read from the epoch-start buffer are accumulated first and those of
 // earlier batches (which may need a wait) after them, each part in list order.
 // The order depends only on the list and the partition, never on timing.
-template <int G, int V, int R, bool BF16>
+template <int G, int V, int R, bool BF16, int kForce>
 __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active, const int32_t* nbr,
                                                 int32_t len, const int32_t* neg, int32_t nneg,
                                                 int32_t k, bool wait, int l, int slot,
                                                 uint32_t* order, const float (&a)[R][V],
                                                 float (&acc)[R][V], WaveCounters& wc) {
-  using T = typename Elem<BF16>::T;
   constexpr int K = ListShape<G>::kIdxPerLane;
   constexpr int kStep = ListShape<G>::kStep;
   constexpr int U = Unroll<G, R>::value < kStep ? Unroll<G, R>::value : kStep;
-  const T* zc = static_cast<const T*>(A.zc);
-  const T* zn = static_cast<const T*>(A.zn);
   const int lane = slot * G + l;
   const uint64_t group_mask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (slot * G));
   const uint64_t below = (1ull << lane) - 1ull;
@@ -233,57 +306,10 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // region 0: rows of the epoch-start buffer (no wait); region 1: rows of
     // earlier batches, each awaited just before it is loaded
-    for (int region = 0; region < 2; ++region) {
-      const int rbeg = region == 0 ? 0 : ncur;
-      const int rlen = region == 0 ? ncur : nnext;
-      for (int jb = 0; __any(jb < rlen); jb += U) {
-        int32_t vid[U];
-        bool pend[U], vn[U], rep[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          const uint32_t e = jb + q < rlen ? my_order[rbeg + jb + q] : kEntNone;
-          vid[q] = (e & kEntVertex) == kEntNone ? -1 : static_cast<int32_t>(e & kEntVertex);
-          pend[q] = vid[q] >= 0 && (e & kEntPending) != 0u;
-          vn[q] = (e & kEntNext) != 0u;
-          rep[q] = (e & kEntRepulsive) != 0u;
-        }
-        if (wait && region == 1) wait_published<U>(A, vid, pend, wc);
-        float y[U][R][V];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          if (vid[q] >= 0) {
-            load_row<G, V, R, BF16>(vn[q] ? zn : zc, vid[q], A.d, l, vn[q], y[q]);
-          } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
-          }
-        }
-        float dq[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
-#pragma unroll
-        for (int q = 0; q < U; ++q) dq[q] = group_sum<G>(dq[q]);
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          if (vid[q] >= 0) {
-            const float c = rep[q] ? repulse_coef(A.force, dq[q], A.eps) : attract_coef(A.force, dq[q]);
-            if (A.force == kSigmoid) {
-#pragma unroll
-              for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, y[q][r][i], acc[r][i]);
-            } else {
-#pragma unroll
-              for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, a[r][i] - y[q][r][i], acc[r][i]);
-            }
-          }
-        }
-      }
-    }
+    for (int jb = 0; __any(jb < ncur); jb += U)
+      accumulate_batch<G, V, R, BF16, kForce, false, U>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
+    for (int jb = 0; __any(jb < nnext); jb += U)
+      accumulate_batch<G, V, R, BF16, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
     // the next step overwrites the order: every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -298,6 +324,7 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
   uint32_t polls = 0;
+#pragma clang loop unroll(disable)
   while (true) {
     if (pend) pend = ld_coherent_u32(flag) == 0u;
     if (!__any(pend)) break;
@@ -373,10 +400,14 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   // attraction over the unit's neighbours, then (whole and late units)
   // repulsion from the batch's shared negatives: Algorithm 2's two loops
   const int32_t nneg = (active && !early) ? A.s : 0;
-  const int32_t* list = (w.kind & kUnitReordered) ? A.pcol : A.colidx;
-  accumulate_unit<G, V, R, BF16>(A, active, list + (active ? w.beg : 0), w.len,
-                                 A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s, nneg,
-                                 w.k, wait, l, slot, order, a, acc, wc);
+  const int32_t* list = ((w.kind & kUnitReordered) ? A.pcol : A.colidx) + (active ? w.beg : 0);
+  const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
+  if (A.force == kSigmoid)
+    accumulate_unit<G, V, R, BF16, kSigmoid>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
+                                             acc, wc);
+  else
+    accumulate_unit<G, V, R, BF16, kStudentT>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
+                                              acc, wc);
 
   // early units: the partial sums are added up a tree of fan-in A.fan_in
   // (level 0 = the units, one root); the last child to arrive at a node sums
