@@ -147,6 +147,8 @@ def main() -> int:
     ap.add_argument("--workload", default="cl1m", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict", "dynamic"])
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+                    help="override the workload's precision (to compare the two forms on one graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -172,6 +174,8 @@ def main() -> int:
         return 1
     t0 = time.perf_counter()
     g, p = gg.workload(args.workload)
+    if args.precision:
+        p["precision"] = args.precision
     log(f"graph {args.workload}: n={g.n} nnz={g.nnz} max degree={int(g.degrees().max())} "
         f"({time.perf_counter() - t0:.1f}s)")
     Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])

@@ -172,7 +172,8 @@ f2v_status f2v_last_epoch_ms(f2v_ctx *ctx, float *update_ms, float *total_ms);
  * waiting for rows of earlier batches to be published, [2] cycles combining
  * split rows, [3] work groups processed, [4] polls that found a row
  * unpublished, [5] waits that had to poll, [6] cycles storing and publishing
- * rows, [7] unused.  f2v_wave_stats copies min(cap_waves, waves) rows of the
+ * rows, [7] cycles of [1] spent in units that take a split row's step.
+ * f2v_wave_stats copies min(cap_waves, waves) rows of the
  * last such epoch to host memory `out` (may be NULL to query the count) and
  * synchronises the stream. */
 f2v_status f2v_set_diagnostics(f2v_ctx *ctx, int32_t enable);

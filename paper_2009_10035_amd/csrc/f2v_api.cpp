@@ -22,6 +22,7 @@ namespace {
 constexpr int kDefaultChunk = 32;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
+constexpr int kMaxBlocksPerCu = 6;
 constexpr uint32_t kSpinLimit = 1u << 21;
 constexpr int64_t kMaxStatWaves = 16384;
 
@@ -89,7 +90,7 @@ Layout layout_of(const f2v_params& p) {
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
   L.trace = take(size_t(n) * 8);
-  L.ticket = take(4);
+  L.ticket = take(size_t(f2v::kMaxClaimClasses) * f2v::kClaimStride * 4);
   L.total = off;
   return L;
 }
@@ -148,6 +149,7 @@ struct f2v_ctx {
   uint16_t* bbuf[2] = {nullptr, nullptr};
   int cur = 0;
   const Variant* var = nullptr;
+  const void* update_fn = nullptr;  // var's update kernel for this d
   int update_grid = 0;
   int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit or the job's size
   int cus = 0;
@@ -160,6 +162,7 @@ struct f2v_ctx {
   int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
   int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
   int32_t late_window = 8;    // batches whose neighbours a split row takes last (F2V_LATE_WINDOW)
+  int32_t claim_classes = 0;  // dataflow: 0 static round robin, else claim classes (F2V_CLAIM_CLASSES)
   int64_t nsplit = 0;         // rows of degree above chunk
   int64_t hub_total = 0;      // combining-tree slots of all split rows
   std::string err;
@@ -266,6 +269,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   c->z_user = d_z;
   c->ws = static_cast<char*>(d_ws);
   c->var = f2v::find_variant(p->d, p->precision == F2V_BF16);
+  c->update_fn = p->d == c->var->g * c->var->v * c->var->r ? c->var->update_full : c->var->update;
   const bool bf16 = p->precision == F2V_BF16;
   c->zbuf[0] = d_z;
   c->zbuf[1] = bf16 ? nullptr : c->at<float>(L.zbuf1);
@@ -285,12 +289,17 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   if ((he = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
   int per_cu = 0;
-  if ((he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->var->update, kBlock, 0)) != hipSuccess)
+  if ((he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->update_fn, kBlock, 0)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("occupancy query: ") + hipGetErrorString(he));
   if (const char* env = std::getenv("F2V_UPDATE_BLOCKS_PER_CU")) {
     const int want = std::atoi(env);
     if (want >= 1 && want < per_cu) per_cu = want;
   }
+  // The dataflow schedule needs every block resident.  With seven blocks per
+  // CU (a kernel instance of 69 VGPRs, for which the occupancy query reports
+  // seven) the cooperative launch was not fully resident on MI355X and waits
+  // ran into their bound; six and fewer were, so the grid stays at six.
+  if (per_cu > kMaxBlocksPerCu) per_cu = kMaxBlocksPerCu;
   if (per_cu < 1) per_cu = 1;
   c->update_grid = per_cu * c->cus;
   // F2V_COOPERATIVE=0 launches the same grid without the cooperative API (some
@@ -302,6 +311,10 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (x >= 4 && x <= 64) c->fan_in = x;
   }
   if (const char* env = std::getenv("F2V_SORT")) c->sort = std::atoi(env) != 0;
+  if (const char* env = std::getenv("F2V_CLAIM_CLASSES")) {
+    const int x = std::atoi(env);
+    if (x >= 0 && x <= f2v::kMaxClaimClasses) c->claim_classes = x;
+  }
   if (const char* env = std::getenv("F2V_LATE_WINDOW")) {
     const int x = std::atoi(env);
     if (x >= 0 && x <= (1 << 20)) c->late_window = x;
@@ -442,8 +455,8 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
   A.spin_limit = kSpinLimit;
-  A.ticket = nullptr;
-  A.claim = 1;
+  A.ticket = c->at<uint32_t>(L.ticket);
+  A.classes = 0;
   A.fan_in = c->fan_in;
   A.wave_stats = nullptr;
   A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
@@ -454,17 +467,17 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (p.schedule == F2V_SCHED_DYNAMIC) {
     A.strict_batch = -1;
-    A.ticket = c->at<uint32_t>(L.ticket);
-    A.claim = 1;
+    A.classes = 1;
     void* args[] = {&A};
-    HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
+    HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
   } else if (p.schedule == F2V_SCHED_DATAFLOW) {
     A.strict_batch = -1;
+    A.classes = c->claim_classes;
     void* args[] = {&A};
     if (c->cooperative)
-      HIP_TRY(c, hipLaunchCooperativeKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+      HIP_TRY(c, hipLaunchCooperativeKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
     else
-      HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+      HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
   } else {
     const int64_t groups_hint = (p.batch + slots - 1) / slots;
     int grid = static_cast<int>((groups_hint + 3) / 4);
@@ -477,7 +490,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
       for (int part = 0; part < (c->nsplit > 0 ? 2 : 1); ++part) {
         A.strict_late = part;
         void* args[] = {&A};
-        HIP_TRY(c, hipLaunchKernel(c->var->update, dim3(grid), dim3(kBlock), args, 0, s));
+        HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(grid), dim3(kBlock), args, 0, s));
       }
     }
   }

@@ -10,6 +10,11 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
+// Claim counters of the claiming schedules: at most kMaxClaimClasses, each
+// in its own 128-byte line.
+constexpr int kMaxClaimClasses = 1024;
+constexpr int kClaimStride = 32;
+
 // Kinds of work unit.  A row of degree at most `chunk` is one WHOLE unit (its
 // neighbours, the batch's negatives, the step).  A longer (split) row has its
 // neighbour list reordered each epoch into an early part and a late part: the
@@ -54,7 +59,7 @@ __host__ __device__ __forceinline__ int64_t tree_nodes(int64_t units, int32_t fa
 // spent waiting for publications, cycles in split-row combines, work groups
 // processed, polls that found a row unpublished, waits that had to poll.
 enum WaveStat { kStatCycles = 0, kStatWaitCycles, kStatCombineCycles, kStatGroups, kStatPolls,
-                kStatWaits, kStatPublishCycles, kWaveStats = 8 };
+                kStatWaits, kStatPublishCycles, kStatWaitLateCycles, kWaveStats = 8 };
 
 // Everything one epoch's update kernel reads or writes.
 struct EpochArgs {
@@ -83,8 +88,8 @@ struct EpochArgs {
   int32_t strict_batch;     // >= 0: process only this batch, no waits
   int32_t strict_late;      // with strict_batch: 0 its whole and early units, 1 its late units
   uint32_t spin_limit;      // bound on polls of one dependency wait
-  uint32_t* ticket;         // non-null: waves claim groups from this counter
-  int32_t claim;            // groups per claim
+  uint32_t* ticket;         // claim counters (kClaimStride words apart), or nullptr
+  int32_t classes;          // > 0: waves claim groups from `classes` counters, else static
   int32_t fan_in;           // fan-in of the combining tree of split rows
 };
 
@@ -114,7 +119,7 @@ struct SetupArgs {
   int32_t* lstart;          // [nb] first ticket of each batch's second part
   Unit* units;
   int32_t* ngroups;
-  uint32_t* ticket;         // claim counter of the dynamic schedule (reset here)
+  uint32_t* ticket;         // claim counters (reset here)
   int64_t n, nsplit;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave
   int32_t late_window;      // batches before a split row's own whose neighbours go late
@@ -143,7 +148,8 @@ struct LossArgs {
 struct Variant {
   int g, v, r;
   bool bf16;
-  const void* update;       // __global__ void(EpochArgs)
+  const void* update;       // __global__ void(EpochArgs), any d <= g * v * r
+  const void* update_full;  // the same for d = g * v * r (no lane past the row's end)
   const void* loss;         // __global__ void(LossArgs)
 };
 

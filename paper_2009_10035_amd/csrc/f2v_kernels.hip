@@ -259,8 +259,8 @@ __global__ void k_batch_starts(SetupArgs A) {
   if (threadIdx.x == 0) {
     A.bstart[A.nb] = static_cast<int32_t>(carry);
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
-    *A.ticket = 0u;
   }
+  for (int i = threadIdx.x; i < kMaxClaimClasses; i += blockDim.x) A.ticket[i * kClaimStride] = 0u;
   __syncthreads();
   __threadfence_block();
   for (int64_t k = threadIdx.x; k < A.nb; k += blockDim.x) {

@@ -52,7 +52,7 @@ struct Unroll {
 // update loop needs) and written out at kernel end.  Every lane applies the
 // same update, so the wave's lanes agree on every value.
 struct WaveCounters {
-  uint64_t wait, combine, publish, groups, polls, waits;
+  uint64_t wait, combine, publish, groups, polls, waits, wait_late;
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
@@ -104,13 +104,15 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
 }
 
 // Row elements owned by lane l of a group: R vectors of V at (r*G + l)*V.
-template <int G, int V, int R, bool BF16>
+// Lanes past the row's end get zeros.  FULL: d = G * V * R, every lane holds
+// elements.
+template <int G, int V, int R, bool BF16, bool FULL = false>
 __device__ __forceinline__ void load_row(const typename Elem<BF16>::T* base, int64_t row, int d,
                                          int l, bool coherent, float (&y)[R][V]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e0 = (r * G + l) * V;
-    if (e0 < d) {
+    if (FULL || e0 < d) {
       const typename Elem<BF16>::T* p = base + row * d + e0;
       if (coherent) load_coherent<V, BF16>(p, y[r]);
       else load_plain<V, BF16>(p, y[r]);
@@ -163,7 +165,7 @@ struct TreeLoads {
 // of a step: rows of the epoch-start buffer (kNext false: plain loads, no
 // wait) or of earlier batches (kNext: awaited, device-scope loads).  Adds each
 // entry's force on the group's row `a` into acc, in entry order.
-template <int G, int V, int R, bool BF16, int kForce, bool kNext, int U>
+template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool kNext, int U>
 __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint32_t* ent, int cnt, bool wait,
                                                  int l, const float (&a)[R][V], float (&acc)[R][V],
                                                  WaveCounters& wc) {
@@ -173,7 +175,9 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
   bool pend[U], rep[U];
 #pragma unroll
   for (int q = 0; q < U; ++q) {
-    const uint32_t e = q < cnt ? ent[q] : kEntNone;
+    uint32_t e = q < cnt ? ent[q] : kEntNone;
+    // one row per wave: the entry is the same in every lane (scalar branches
+    // and addresses)
     vid[q] = (e & kEntVertex) == kEntNone ? -1 : static_cast<int32_t>(e & kEntVertex);
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
@@ -183,7 +187,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
 #pragma unroll
   for (int q = 0; q < U; ++q) {
     if (vid[q] >= 0) {
-      load_row<G, V, R, BF16>(src, vid[q], A.d, l, kNext, y[q]);
+      load_row<G, V, R, BF16, FULL>(src, vid[q], A.d, l, kNext, y[q]);
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -240,7 +244,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
 // entries read from the epoch-start buffer are accumulated first and those of
 // earlier batches (which may need a wait) after them, each part in list order.
 // The order depends only on the list and the partition, never on timing.
-template <int G, int V, int R, bool BF16, int kForce>
+template <int G, int V, int R, bool BF16, bool FULL, int kForce>
 __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active, const int32_t* nbr,
                                                 int32_t len, const int32_t* neg, int32_t nneg,
                                                 int32_t k, bool wait, int l, int slot,
@@ -307,9 +311,9 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
     // region 0: rows of the epoch-start buffer (no wait); region 1: rows of
     // earlier batches, each awaited just before it is loaded
     for (int jb = 0; __any(jb < ncur); jb += U)
-      accumulate_batch<G, V, R, BF16, kForce, false, U>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, false, U>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
     for (int jb = 0; __any(jb < nnext); jb += U)
-      accumulate_batch<G, V, R, BF16, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
     // the next step overwrites the order: every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -347,19 +351,19 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
 }
 
 // Store the lane's part of a partial-sum row.
-template <int G, int V, int R>
+template <int G, int V, int R, bool FULL>
 __device__ __forceinline__ void store_partial(float* row, int d, int l, const float (&acc)[R][V]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e0 = (r * G + l) * V;
-    if (e0 < d) store_coherent_f32<V>(row + e0, acc[r]);
+    if (FULL || e0 < d) store_coherent_f32<V>(row + e0, acc[r]);
   }
 }
 
 // One work unit (see the unit kinds): accumulate its list, then either take
 // the step of Eq. 10 and publish the row (whole and late units) or add the
 // partial sum into the row's combining tree (early units).
-template <int G, int V, int R, bool BF16>
+template <int G, int V, int R, bool BF16, bool FULL>
 __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
                                              bool wait, uint32_t* order, WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
@@ -374,13 +378,29 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 #pragma unroll
     for (int i = 0; i < V; ++i) acc[r][i] = 0.0f;
   if (active) {
-    load_row<G, V, R, BF16>(static_cast<const T*>(A.zc), u, A.d, l, false, a);
+    load_row<G, V, R, BF16, FULL>(static_cast<const T*>(A.zc), u, A.d, l, false, a);
   } else {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int i = 0; i < V; ++i) a[r][i] = 0.0f;
   }
+  // BF16 form: the FP32 master row the step updates, fetched with the row
+  // (its load would otherwise sit between the forces and the publication)
+  float m[BF16 ? R : 1][V];
+  if constexpr (BF16) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e0 = (r * G + l) * V;
+      if (active && !early && (FULL || e0 < A.d)) {
+        load_plain_f32<V>(A.master + static_cast<int64_t>(u) * A.d + e0, m[r]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) m[r][i] = 0.0f;
+      }
+    }
+  }
+  const uint64_t wait_before = A.wave_stats ? wc.wait : 0;
   // late unit: start from the early part's sum (the root of its tree), once
   // its flag is set
   const bool has_early = late && w.nch > 0;
@@ -392,7 +412,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e0 = (r * G + l) * V;
-        if (e0 < A.d) load_coherent<V, false>(root + e0, acc[r]);
+        if ((FULL || e0 < A.d)) load_coherent<V, false>(root + e0, acc[r]);
       }
     }
   }
@@ -403,11 +423,13 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const int32_t* list = ((w.kind & kUnitReordered) ? A.pcol : A.colidx) + (active ? w.beg : 0);
   const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
   if (A.force == kSigmoid)
-    accumulate_unit<G, V, R, BF16, kSigmoid>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
+    accumulate_unit<G, V, R, BF16, FULL, kSigmoid>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
                                              acc, wc);
   else
-    accumulate_unit<G, V, R, BF16, kStudentT>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
+    accumulate_unit<G, V, R, BF16, FULL, kStudentT>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
                                               acc, wc);
+
+  if (A.wave_stats && __any(late)) wc.wait_late += wc.wait - wait_before;
 
   // early units: the partial sums are added up a tree of fan-in A.fan_in
   // (level 0 = the units, one root); the last child to arrive at a node sums
@@ -419,7 +441,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
     const int64_t base = early ? A.hub_base[u] : 0;
     bool climbing = early && w.nch > 1;
     bool flag_it = early && w.nch == 1;
-    if (early) store_partial<G, V, R>(A.hub_part + (base + w.c) * A.d, A.d, l, acc);
+    if (early) store_partial<G, V, R, FULL>(A.hub_part + (base + w.c) * A.d, A.d, l, acc);
     drain_memory();
     const int32_t fan = A.fan_in;
     int32_t node = w.c, count = w.nch, off = 0;  // current node and its level's size/offset
@@ -447,7 +469,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
               const int e0 = (r * G + l) * V;
-              if (j0 + j < nchild && e0 < A.d) {
+              if (j0 + j < nchild && (FULL || e0 < A.d)) {
                 load_coherent<V, false>(kids + static_cast<int64_t>(j0 + j) * A.d + e0, t[j][r]);
               } else {
 #pragma unroll
@@ -474,7 +496,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
                 for (int q = 0; q < V; ++q) acc[r][q] += t[j][r][q];
             }
         }
-        store_partial<G, V, R>(A.hub_part + (base + poff + parent) * A.d, A.d, l, acc);
+        store_partial<G, V, R, FULL>(A.hub_part + (base + poff + parent) * A.d, A.d, l, acc);
       }
       climbing = last && pcount > 1;
       if (last && pcount == 1) flag_it = true;
@@ -494,14 +516,12 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e0 = (r * G + l) * V;
-      if (e0 < A.d) {
+      if ((FULL || e0 < A.d)) {
         float nw[V];
         if constexpr (BF16) {
-          float m[V];
           float* mp = A.master + static_cast<int64_t>(u) * A.d + e0;
-          load_plain_f32<V>(mp, m);
 #pragma unroll
-          for (int i = 0; i < V; ++i) nw[i] = m[i] - A.lr * acc[r][i];
+          for (int i = 0; i < V; ++i) nw[i] = m[r][i] - A.lr * acc[r][i];
           store_plain_f32<V>(mp, nw);
           store_coherent_bf16<V>(static_cast<uint16_t*>(A.zn) + static_cast<int64_t>(u) * A.d + e0, nw);
         } else {
@@ -524,7 +544,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   }
 }
 
-template <int G, int V, int R, bool BF16>
+template <int G, int V, int R, bool BF16, bool FULL>
 __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
   constexpr int S = 64 / G;
   // per-wave LDS for the reordered entries of a step (64 * kIdxPerLane words)
@@ -548,36 +568,42 @@ __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
   }
   __shared__ WaveCounters wc_lds[4];
   WaveCounters& wc = wc_lds[threadIdx.x >> 6];
-  if (A.wave_stats || A.trace) wc = WaveCounters{0, 0, 0, 0, 0, 0, 0};
+  if (A.wave_stats || A.trace) wc = WaveCounters{0, 0, 0, 0, 0, 0, 0, 0};
   const uint64_t t_start = A.wave_stats ? clock64() : 0;
-  if (A.ticket) {
-    // dynamic: claim `claim` consecutive groups at a time, in batch order
-    while (true) {
-      uint32_t g0 = 0;
-      if (lane == 0) g0 = atomicAdd(A.ticket, static_cast<uint32_t>(A.claim));
-      g0 = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(g0)));
-      if (g0 >= static_cast<uint32_t>(gend)) break;
-      const int g1 = static_cast<int>(g0) + A.claim < gend ? static_cast<int>(g0) + A.claim : gend;
-      for (int g = static_cast<int>(g0); g < g1; ++g) {
-        const Unit w = A.units[static_cast<int64_t>(g) * S + slot];
-        process_unit<G, V, R, BF16>(A, w, l, slot, wait, order, wc);
-      }
+  // Groups a wave processes, in increasing order: static, g = gbeg + wave +
+  // i * nwaves; or claiming, the groups c, c + C, c + 2C, ... of its class
+  // c = wave % C in the order its class's counter hands them out.  One group
+  // ahead is known (its unit record loads while the current one is processed).
+  const int cls = A.classes > 0 ? wave % A.classes : 0;
+  uint32_t* ctr = A.ticket + static_cast<int64_t>(cls) * kClaimStride;
+  auto following = [&](int g) {
+    int64_t t;
+    if (A.classes > 0) {
+      uint32_t x = 0;
+      if (lane == 0) x = atomicAdd(ctr, 1u);
+      x = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+      t = cls + static_cast<int64_t>(A.classes) * x;
+    } else {
+      t = static_cast<int64_t>(g) + nwaves;
     }
-  } else {
-    int g = gbeg + wave;
-    Unit cur{};
-    cur.u = -1;
-    if (g < gend) cur = A.units[static_cast<int64_t>(g) * S + slot];
-    while (g < gend) {
-      // fetch the next group's unit while this one is processed
-      const int gn = g + nwaves;
-      Unit nxt{};
-      nxt.u = -1;
-      if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
-      process_unit<G, V, R, BF16>(A, cur, l, slot, wait, order, wc);
-      cur = nxt;
-      g = gn;
-    }
+    return t < gend ? static_cast<int>(t) : gend;
+  };
+  // (group indices are wave-uniform; readfirstlane lets the compiler keep
+  // them and the unit records in scalar registers)
+  int g = __builtin_amdgcn_readfirstlane(following(gbeg + wave - nwaves));
+  int gn = __builtin_amdgcn_readfirstlane(g < gend ? following(g) : gend);
+  Unit cur{};
+  cur.u = -1;
+  if (g < gend) cur = A.units[static_cast<int64_t>(g) * S + slot];
+  while (g < gend) {
+    Unit nxt{};
+    nxt.u = -1;
+    if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
+    const int gnn = __builtin_amdgcn_readfirstlane(gn < gend ? following(gn) : gend);
+    process_unit<G, V, R, BF16, FULL>(A, cur, l, slot, wait, order, wc);
+    cur = nxt;
+    g = gn;
+    gn = gnn;
   }
   if (A.wave_stats && lane == 0) {
     uint64_t* o = A.wave_stats + static_cast<int64_t>(wave) * kWaveStats;
@@ -588,6 +614,7 @@ __global__ __launch_bounds__(256) void k_update(EpochArgs A) {
     o[kStatPolls] = wc.polls;
     o[kStatWaits] = wc.waits;
     o[kStatPublishCycles] = wc.publish;
+    o[kStatWaitLateCycles] = wc.wait_late;
   }
 }
 

@@ -4,7 +4,8 @@
 namespace f2v {
 
 #define F2V_VARIANT(G, V, R, B) \
-  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B>), \
+  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B, false>), \
+          reinterpret_cast<const void*>(&k_update<G, V, R, B, true>), \
           reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
 
 extern const Variant kVariants_f32_v2[] = {
