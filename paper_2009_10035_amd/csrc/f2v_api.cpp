@@ -161,7 +161,7 @@ struct f2v_ctx {
   bool record_events = true;  // off while a server captures the context's work into a graph
   int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
   int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
-  int32_t late_window = 8;    // batches whose neighbours a split row takes last (F2V_LATE_WINDOW)
+  int32_t late_window = 24;   // batches whose neighbours a split row takes last (F2V_LATE_WINDOW)
   int32_t claim_classes = 0;  // dataflow: 0 static round robin, else claim classes (F2V_CLAIM_CLASSES)
   int64_t nsplit = 0;         // rows of degree above chunk
   int64_t hub_total = 0;      // combining-tree slots of all split rows
@@ -458,6 +458,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.ticket = c->at<uint32_t>(L.ticket);
   A.classes = 0;
   A.fan_in = c->fan_in;
+  A.late_window = c->late_window;
   A.wave_stats = nullptr;
   A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
   if (c->diagnostics && p.schedule != F2V_SCHED_STRICT && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {

@@ -91,6 +91,7 @@ struct EpochArgs {
   uint32_t* ticket;         // claim counters (kClaimStride words apart), or nullptr
   int32_t classes;          // > 0: waves claim groups from `classes` counters, else static
   int32_t fan_in;           // fan-in of the combining tree of split rows
+  int32_t late_window;      // batches before a unit's own whose rows are taken last
 };
 
 // Prologue of an epoch (random partition, negatives, split-row lists, work

@@ -95,6 +95,50 @@ __global__ void k_split_lists(SetupArgs A) {
   }
 }
 
+// Longest late part (entries) and widest window sorted by k_sort_late.
+constexpr int kSortLateMax = 64 * kSplitTile;
+constexpr int kSortLateWindow = 32;
+
+// K1a': one wave per split row: its late part in batch order, oldest batch
+// first (ties in the part's order), so that the entries a late unit waits
+// for last are loaded last.  Parts longer than kSortLateMax, or windows wider
+// than kSortLateWindow, keep their order.
+__global__ void k_sort_late(SetupArgs A) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  if (A.late_window > kSortLateWindow) return;
+  for (int64_t i = wave; i < A.nsplit; i += nwaves) {
+    const int32_t u = A.split_ids[i];
+    const int32_t k = static_cast<int32_t>(A.word[u]);
+    const int64_t r1 = A.rowptr[u + 1];
+    const int64_t nl = r1 - A.rowptr[u] - A.ecnt[u];
+    if (nl < 2 || nl > kSortLateMax) continue;
+    const int64_t lb = r1 - nl;
+    int32_t x[kSplitTile], key[kSplitTile];
+#pragma unroll
+    for (int j = 0; j < kSplitTile; ++j) {
+      const int64_t idx = j * 64 + lane;
+      x[j] = idx < nl ? A.pcol[lb + idx] : -1;
+    }
+    // batch offset inside the window: k - W <= batch < k for every late entry
+#pragma unroll
+    for (int j = 0; j < kSplitTile; ++j)
+      key[j] = x[j] >= 0 ? static_cast<int32_t>(A.word[x[j]]) - (k - A.late_window) : -1;
+    int64_t pos = 0;
+    for (int b = 0; b < A.late_window; ++b) {
+#pragma unroll
+      for (int j = 0; j < kSplitTile; ++j) {
+        const bool mine = key[j] == b;
+        const uint64_t m = __ballot(mine);
+        if (mine) A.pcol[lb + pos + __popcll(m & below)] = x[j];
+        pos += __popcll(m);
+      }
+    }
+  }
+}
+
 // K1b: 16 lanes per position: the latest earlier batch among the row's
 // neighbours (the batch whose publication it will wait for last).
 __global__ void k_readiness(SetupArgs A, const int32_t* colidx) {
@@ -497,7 +541,10 @@ int grid_for(int64_t work, int threads) {
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(a.n > nneg ? a.n : nneg, 256)), dim3(256), 0, st, a);
-  if (a.nsplit > 0) hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
+  if (a.nsplit > 0) {
+    hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
+  }
   if (a.sort) hipLaunchKernelGGL(k_readiness, dim3((a.n * 16 + 255) / 256), dim3(256), 0, st, a, a.colidx);
   hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
   hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);

@@ -263,46 +263,55 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
     if (!__any(more)) break;
     // entries e = off + l + i*G of this step, their source buffer and state
     uint32_t ent[K];
-    bool cur[K], nxt[K];
+    bool cur[K], old[K], rec[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int32_t e = off + l + i * G;
       const bool valid = more && e < total;
       const int32_t v = !valid ? -1 : (e < len ? nbr[e] : neg[e - len]);
       ent[i] = kEntNone;
-      cur[i] = nxt[i] = false;
+      cur[i] = old[i] = rec[i] = false;
       if (valid) {
         const uint32_t wd = ld_coherent_u32(A.word + v);
-        const bool from_next = static_cast<int32_t>(wd & ~kPublished) < k;
+        const int32_t kb = static_cast<int32_t>(wd & ~kPublished);
+        const bool from_next = kb < k;
         ent[i] = static_cast<uint32_t>(v) | (e >= len ? kEntRepulsive : 0u) |
                  (from_next ? kEntNext : 0u) |
                  ((wait && from_next && (wd & kPublished) == 0u) ? kEntPending : 0u);
         cur[i] = !from_next;
-        nxt[i] = from_next;
+        rec[i] = from_next && kb >= k - A.late_window;
+        old[i] = from_next && !rec[i];
       }
     }
-    // positions in the reordered step: epoch-start rows, then earlier-batch
-    // rows, then empty slots, each in list order
-    uint64_t bc[K], bn[K];
-    int ncur = 0, nnext = 0;
+    // positions in the reordered step: epoch-start rows, then rows of batches
+    // more than late_window before this one, then rows of the last
+    // late_window batches (the ones still being written), then empty slots,
+    // each in list order
+    uint64_t bc[K], bo[K], br[K];
+    int ncur = 0, nold = 0, nrec = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       bc[i] = __ballot(cur[i]) & group_mask;
-      bn[i] = __ballot(nxt[i]) & group_mask;
+      bo[i] = __ballot(old[i]) & group_mask;
+      br[i] = __ballot(rec[i]) & group_mask;
       ncur += __popcll(bc[i]);
-      nnext += __popcll(bn[i]);
+      nold += __popcll(bo[i]);
+      nrec += __popcll(br[i]);
     }
-    int before_c = 0, before_n = 0, before_x = 0;
+    const int nnext = nold + nrec;
+    int before_c = 0, before_o = 0, before_r = 0, before_x = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const uint64_t bx = group_mask & ~bc[i] & ~bn[i];
+      const uint64_t bx = group_mask & ~bc[i] & ~bo[i] & ~br[i];
       int pos;
       if (cur[i]) pos = before_c + __popcll(bc[i] & below);
-      else if (nxt[i]) pos = ncur + before_n + __popcll(bn[i] & below);
+      else if (old[i]) pos = ncur + before_o + __popcll(bo[i] & below);
+      else if (rec[i]) pos = ncur + nold + before_r + __popcll(br[i] & below);
       else pos = ncur + nnext + before_x + __popcll(bx & below);
       my_order[pos] = ent[i];
       before_c += __popcll(bc[i]);
-      before_n += __popcll(bn[i]);
+      before_o += __popcll(bo[i]);
+      before_r += __popcll(br[i]);
       before_x += __popcll(bx);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
