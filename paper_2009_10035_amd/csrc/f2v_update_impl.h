@@ -95,6 +95,9 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
     else __builtin_amdgcn_s_sleep(16);
   }
   compiler_fence();
+  // the unit waited on the chain of publications: finish it ahead of waves
+  // doing work that nothing waits for yet
+  __builtin_amdgcn_s_setprio(2);
   if (A.wave_stats) {
     wc.wait += clock64() - t0;
     wc.polls += polls;
@@ -547,6 +550,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
     A.trace[2 * static_cast<int64_t>(u)] = static_cast<uint32_t>(wc.last_wait_end);
     A.trace[2 * static_cast<int64_t>(u) + 1] = static_cast<uint32_t>(wall_clock64());
   }
+  __builtin_amdgcn_s_setprio(0);
   if (A.wave_stats) {
     wc.publish += clock64() - tp;
     wc.groups += 1;
