@@ -181,6 +181,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     uint32_t e = q < cnt ? ent[q] : kEntNone;
     // one row per wave: the entry is the same in every lane (scalar branches
     // and addresses)
+    if constexpr (G == 64) e = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(e)));
     vid[q] = (e & kEntVertex) == kEntNone ? -1 : static_cast<int32_t>(e & kEntVertex);
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;

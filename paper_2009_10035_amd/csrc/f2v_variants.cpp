@@ -28,18 +28,20 @@ static int min_lanes() {
   return value;
 }
 
-// Preferred V: 8 bytes per lane and load (2 FP32 or 4 bf16 elements);
-// F2V_MAX_VEC = 1, 2 or 4 overrides it.  Measured on MI355X: Chung-Lu 1M,
-// d = 128 FP32: 9.4 ms per epoch with 64 lanes x float2 per row, 10.1 ms with
-// 32 lanes x float4 (fewer rows per wave wait on each other less); SBM 4M,
-// d = 128 bf16: 27.9 ms with 32 lanes x 4 bf16, 33.5 ms with 64 lanes x 2.
-static int max_vec(bool bf16) {
+// Preferred V: 2 elements per lane and load (8 bytes FP32, 4 bytes bf16), so
+// that d = 128 gets one row per wave; F2V_MAX_VEC = 1, 2 or 4 overrides it.
+// Measured on MI355X: Chung-Lu 1M, d = 128 FP32: 3.59 ms per epoch with 64
+// lanes x float2 per row, 4.09 ms with 32 lanes x float4; SBM 4M, d = 128
+// bf16: 23.8 ms with 64 lanes x 2 bf16, 26.9 ms with 32 lanes x 4 (one row
+// per wave keeps rows of one wave from waiting on each other and needs fewer
+// registers).
+static int max_vec(bool) {
   static const int forced = [] {
     const char* env = std::getenv("F2V_MAX_VEC");
     const int x = env ? std::atoi(env) : 0;
     return (x == 1 || x == 2 || x == 4) ? x : 0;
   }();
-  return forced ? forced : (bf16 ? 4 : 2);
+  return forced ? forced : 2;
 }
 
 static const Variant* lookup(int d, bool bf16, int v) {
