@@ -29,7 +29,7 @@ constexpr int64_t kMaxStatWaves = 16384;
 thread_local std::string g_error;
 
 struct Layout {
-  size_t zbuf1, bbuf0, bbuf1, perm, word, split_ids, pcol, ecnt, uoff, eoff, loff, dkey, order, negs, wreal,
+  size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, dkey, order, negs, wreal,
       ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch,
       scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket, total;
   int64_t nb, tmap_cap, hub_slot_cap;
@@ -59,6 +59,7 @@ Layout layout_of(const f2v_params& p) {
   L.bbuf1 = take(bf16 ? size_t(n) * d * 2 : 0);
   L.perm = take(size_t(n) * 4);
   L.word = take(size_t(n) * 4);
+  L.bat = take(L.nb <= 65536 ? size_t(n) * 2 : 0);
   L.split_ids = take(size_t(n) * 4);
   L.pcol = take(size_t(p.nnz) * 4);
   L.ecnt = take(size_t(n) * 4);
@@ -387,6 +388,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.order = c->at<int32_t>(L.order);
   sa.perm = c->at<int32_t>(L.perm);
   sa.word = c->at<uint32_t>(L.word);
+  sa.bat = L.nb <= 65536 ? c->at<uint16_t>(L.bat) : nullptr;
   sa.split_ids = c->at<int32_t>(L.split_ids);
   sa.pcol = c->at<int32_t>(L.pcol);
   sa.ecnt = c->at<int32_t>(L.ecnt);

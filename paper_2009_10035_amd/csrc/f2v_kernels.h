@@ -101,6 +101,8 @@ struct SetupArgs {
   const int32_t* colidx;
   int32_t* perm;            // position -> vertex
   uint32_t* word;           // vertex -> batch index (unpublished)
+  uint16_t* bat;            // vertex -> batch index when nb <= 65536, else nullptr (a
+                            // smaller copy of word for the prologue's random lookups)
   const int32_t* split_ids; // [nsplit] vertices of degree above chunk
   int32_t* pcol;            // [nnz] split rows' lists: early part, then late part
   int32_t* ecnt;            // vertex -> length of the early part of its list (split rows)

@@ -43,6 +43,7 @@ __global__ void k_setup_positions(SetupArgs A) {
       const int32_t v = A.identity ? static_cast<int32_t>(i) : feistel_permute(f, i);
       A.perm[i] = v;
       A.word[v] = static_cast<uint32_t>(i / A.b);
+      if (A.bat) A.bat[v] = static_cast<uint16_t>(i / A.b);
     }
     if (i < nneg) {
       const uint32_t k = static_cast<uint32_t>(i / A.s), j = static_cast<uint32_t>(i % A.s);
@@ -56,42 +57,85 @@ __global__ void k_setup_positions(SetupArgs A) {
 // that eight index and word loads per lane are in flight together).
 constexpr int kSplitTile = 8;
 
-// K1a: one wave per split row: reorder its list into pcol, the early part
-// (neighbours of later batches, of the row's own batch, or of batches more
-// than late_window before it) from the front in list order, the late part
-// from the back.  Both orders depend only on the list and the partition.
+// Batch of vertex v this epoch (prologue lookups).
+__device__ __forceinline__ int32_t batch_of(const SetupArgs& A, int32_t v) {
+  return A.bat ? static_cast<int32_t>(A.bat[v]) : static_cast<int32_t>(A.word[v]);
+}
+
+// Split rows of at most this many entries are reordered by 16 lanes (four rows
+// per wave at once), longer ones by a whole wave.
+constexpr int kSmallSplit = 16 * kSplitTile;
+
+// Reorder the list of split row u (batch k, entries [r0, r1)) with the lanes
+// in `gmask` (this lane is one of them; `below` its lower lanes), `width`
+// lanes at lane index li, `tiles` rounds of kSplitTile entries per lane:
+// early part from the front, late part from the back, both in list order.
+// Returns the early part's length.
+__device__ __forceinline__ int64_t reorder_list(const SetupArgs& A, int32_t k, int64_t r0, int64_t r1,
+                                                bool active, uint64_t gmask, uint64_t below, int width,
+                                                int li) {
+  int64_t ne = 0, nl = 0;
+  for (int64_t base = r0; __any(active && base < r1); base += int64_t{width} * kSplitTile) {
+    int32_t v[kSplitTile], kb[kSplitTile];
+#pragma unroll
+    for (int j = 0; j < kSplitTile; ++j) {
+      const int64_t e = base + j * width + li;
+      v[j] = (active && e < r1) ? A.colidx[e] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kSplitTile; ++j) kb[j] = v[j] >= 0 ? batch_of(A, v[j]) : 0;
+#pragma unroll
+    for (int j = 0; j < kSplitTile; ++j) {
+      const bool valid = v[j] >= 0;
+      const bool late = valid && kb[j] < k && kb[j] >= k - A.late_window;
+      const bool early = valid && !late;
+      const uint64_t me = __ballot(early) & gmask, ml = __ballot(late) & gmask;
+      if (early) A.pcol[r0 + ne + __popcll(me & below)] = v[j];
+      if (late) A.pcol[r1 - 1 - (nl + __popcll(ml & below))] = v[j];
+      ne += __popcll(me);
+      nl += __popcll(ml);
+    }
+  }
+  return ne;
+}
+
+// K1a: the split rows' lists, reordered: the early part (neighbours of later
+// batches, of the row's own batch, or of batches more than late_window before
+// it) from the front in list order, the late part from the back.  Both orders
+// depend only on the list and the partition.  A wave takes four rows at a
+// time: rows of at most kSmallSplit entries are done by 16 lanes each, at
+// once; longer ones by the whole wave, one after the other.
 __global__ void k_split_lists(SetupArgs A) {
   const int lane = threadIdx.x & 63;
+  const int grp = lane >> 4, l16 = lane & 15;
   const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t gmask = 0xffffull << (grp * 16);
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-  for (int64_t i = wave; i < A.nsplit; i += nwaves) {
-    const int32_t u = A.split_ids[i];
-    const int32_t k = static_cast<int32_t>(A.word[u]);
-    const int64_t r0 = A.rowptr[u], r1 = A.rowptr[u + 1];
-    int64_t ne = 0, nl = 0;
-    for (int64_t base = r0; base < r1; base += 64 * kSplitTile) {
-      int32_t v[kSplitTile], kb[kSplitTile];
-#pragma unroll
-      for (int j = 0; j < kSplitTile; ++j) {
-        const int64_t e = base + j * 64 + lane;
-        v[j] = e < r1 ? A.colidx[e] : -1;
-      }
-#pragma unroll
-      for (int j = 0; j < kSplitTile; ++j) kb[j] = v[j] >= 0 ? static_cast<int32_t>(A.word[v[j]]) : 0;
-#pragma unroll
-      for (int j = 0; j < kSplitTile; ++j) {
-        const bool valid = v[j] >= 0;
-        const bool late = valid && kb[j] < k && kb[j] >= k - A.late_window;
-        const bool early = valid && !late;
-        const uint64_t me = __ballot(early), ml = __ballot(late);
-        if (early) A.pcol[r0 + ne + __popcll(me & below)] = v[j];
-        if (late) A.pcol[r1 - 1 - (nl + __popcll(ml & below))] = v[j];
-        ne += __popcll(me);
-        nl += __popcll(ml);
-      }
+  for (int64_t i0 = wave * 4; i0 < A.nsplit; i0 += nwaves * 4) {
+    const int64_t i = i0 + grp;
+    int32_t u = -1, k = 0;
+    int64_t r0 = 0, r1 = 0;
+    if (i < A.nsplit) {
+      u = A.split_ids[i];
+      k = static_cast<int32_t>(A.word[u]);
+      r0 = A.rowptr[u];
+      r1 = A.rowptr[u + 1];
     }
-    if (lane == 0) A.ecnt[u] = static_cast<int32_t>(ne);
+    const bool small = u >= 0 && r1 - r0 <= kSmallSplit;
+    const int64_t ne = reorder_list(A, k, r0, r1, small, gmask, below, 16, l16);
+    if (small && l16 == 0) A.ecnt[u] = static_cast<int32_t>(ne);
+    // long rows: the whole wave, one row after the other (scalar loop)
+    uint64_t longs = __ballot(u >= 0 && !small && l16 == 0);
+    while (longs != 0) {
+      const int g = __builtin_ctzll(longs);
+      longs &= longs - 1;
+      const int32_t lu = __builtin_amdgcn_readlane(u, g);
+      const int32_t lk = __builtin_amdgcn_readlane(k, g);
+      const int64_t lr0 = A.rowptr[lu], lr1 = A.rowptr[lu + 1];
+      const int64_t lne = reorder_list(A, lk, lr0, lr1, true, ~0ull, below, 64, lane);
+      if (lane == 0) A.ecnt[lu] = static_cast<int32_t>(lne);
+    }
   }
 }
 
@@ -99,41 +143,63 @@ __global__ void k_split_lists(SetupArgs A) {
 constexpr int kSortLateMax = 64 * kSplitTile;
 constexpr int kSortLateWindow = 32;
 
-// K1a': one wave per split row: its late part in batch order, oldest batch
-// first (ties in the part's order), so that the entries a late unit waits
-// for last are loaded last.  Parts longer than kSortLateMax, or windows wider
-// than kSortLateWindow, keep their order.
+// Split rows a wave of k_sort_late looks at.
+constexpr int kSortRowsPerWave = 8;
+
+// K1a': the late part of every split row in batch order, oldest batch first
+// (ties in the part's order), so that the entries a late unit waits for last
+// are loaded last.  Each of the first kSortRowsPerWave lanes looks up one row;
+// the wave then sorts the rows whose late part has two or more entries, one
+// after the other.  Parts
+// longer than kSortLateMax, or windows wider than kSortLateWindow, keep their
+// order.
 __global__ void k_sort_late(SetupArgs A) {
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
   if (A.late_window > kSortLateWindow) return;
-  for (int64_t i = wave; i < A.nsplit; i += nwaves) {
-    const int32_t u = A.split_ids[i];
-    const int32_t k = static_cast<int32_t>(A.word[u]);
-    const int64_t r1 = A.rowptr[u + 1];
-    const int64_t nl = r1 - A.rowptr[u] - A.ecnt[u];
-    if (nl < 2 || nl > kSortLateMax) continue;
-    const int64_t lb = r1 - nl;
-    int32_t x[kSplitTile], key[kSplitTile];
-#pragma unroll
-    for (int j = 0; j < kSplitTile; ++j) {
-      const int64_t idx = j * 64 + lane;
-      x[j] = idx < nl ? A.pcol[lb + idx] : -1;
+  for (int64_t i0 = wave * kSortRowsPerWave; i0 < A.nsplit; i0 += nwaves * kSortRowsPerWave) {
+    const int64_t i = i0 + lane;
+    int32_t u = 0;
+    int64_t nl = 0;
+    if (lane < kSortRowsPerWave && i < A.nsplit) {
+      u = A.split_ids[i];
+      nl = A.rowptr[u + 1] - A.rowptr[u] - A.ecnt[u];
     }
-    // batch offset inside the window: k - W <= batch < k for every late entry
-#pragma unroll
-    for (int j = 0; j < kSplitTile; ++j)
-      key[j] = x[j] >= 0 ? static_cast<int32_t>(A.word[x[j]]) - (k - A.late_window) : -1;
-    int64_t pos = 0;
-    for (int b = 0; b < A.late_window; ++b) {
+    uint64_t todo = __ballot(nl >= 2 && nl <= kSortLateMax);
+    while (todo != 0) {
+      const int src = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t su = __builtin_amdgcn_readlane(u, src);
+      const int64_t r1 = A.rowptr[su + 1];
+      const int64_t snl = r1 - A.rowptr[su] - A.ecnt[su];
+      const int32_t k = static_cast<int32_t>(A.word[su]);
+      const int64_t lb = r1 - snl;
+      int32_t x[kSplitTile], key[kSplitTile];
 #pragma unroll
       for (int j = 0; j < kSplitTile; ++j) {
-        const bool mine = key[j] == b;
-        const uint64_t m = __ballot(mine);
-        if (mine) A.pcol[lb + pos + __popcll(m & below)] = x[j];
-        pos += __popcll(m);
+        const int64_t idx = j * 64 + lane;
+        x[j] = idx < snl ? A.pcol[lb + idx] : -1;
+      }
+      // batch offset inside the window: k - W <= batch < k for every late entry
+#pragma unroll
+      for (int j = 0; j < kSplitTile; ++j)
+        key[j] = x[j] >= 0 ? batch_of(A, x[j]) - (k - A.late_window) : -1;
+      // counting sort over the window's batches, tile by tile (tiles of 64
+      // entries; most late parts fit in one)
+      const int tiles = static_cast<int>((snl + 63) / 64);
+      int64_t pos = 0;
+      for (int b = 0; b < A.late_window; ++b) {
+#pragma unroll
+        for (int j = 0; j < kSplitTile; ++j) {
+          if (j < tiles) {
+            const bool mine = key[j] == b;
+            const uint64_t m = __ballot(mine);
+            if (mine) A.pcol[lb + pos + __popcll(m & below)] = x[j];
+            pos += __popcll(m);
+          }
+        }
       }
     }
   }
@@ -542,8 +608,9 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(a.n > nneg ? a.n : nneg, 256)), dim3(256), 0, st, a);
   if (a.nsplit > 0) {
-    hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * 64, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 16, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * (64 / kSortRowsPerWave), 256)), dim3(256), 0, st,
+                       a);
   }
   if (a.sort) hipLaunchKernelGGL(k_readiness, dim3((a.n * 16 + 255) / 256), dim3(256), 0, st, a, a.colidx);
   hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
