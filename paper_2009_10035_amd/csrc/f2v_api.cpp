@@ -23,7 +23,11 @@ constexpr int kDefaultChunk = 32;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocksPerCu = 6;
-constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr int64_t kDynamicLookahead = 8;
+// Bound on one dependency wait: 10 s of the device's 100 MHz constant clock.
+// Waits end long before it unless the epoch cannot complete; concurrent jobs
+// can slow a wait down by far more than any poll count would allow for.
+constexpr uint64_t kSpinTicks = 1000000000ull;
 constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
@@ -321,9 +325,17 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (x >= 0 && x <= (1 << 20)) c->late_window = x;
   }
   {
-    // enough waves for about four groups each, at most the occupancy limit
-    const int64_t groups = (L.tmap_cap + slots_of(c->var) - 1) / slots_of(c->var);
-    int64_t blocks = (groups + 4 * (kBlock / 64) - 1) / (4 * (kBlock / 64));
+    // The dynamic schedule (jobs sharing the device) gets one wave per group
+    // of about kDynamicLookahead batches, at most the occupancy limit: a
+    // batch's units can only run once the batches just before it are done,
+    // so more waves would mostly poll while other jobs need the CUs.
+    // F2V_DYNAMIC_LOOKAHEAD overrides the lookahead (0: the occupancy limit).
+    int64_t lookahead = kDynamicLookahead;
+    if (const char* env = std::getenv("F2V_DYNAMIC_LOOKAHEAD")) lookahead = std::atoi(env);
+    const int64_t slots = slots_of(c->var);
+    const int64_t per_batch = (int64_t(p->batch) * 5 / 4 + slots - 1) / slots;  // units incl. splits
+    const int64_t groups = lookahead > 0 ? lookahead * per_batch : (L.tmap_cap + slots - 1) / slots;
+    int64_t blocks = (groups + (kBlock / 64) - 1) / (kBlock / 64);
     if (blocks < 1) blocks = 1;
     if (blocks > c->update_grid) blocks = c->update_grid;
     c->dynamic_grid = static_cast<int>(blocks);
@@ -456,7 +468,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.force = p.force;
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
-  A.spin_limit = kSpinLimit;
+  A.spin_ticks = kSpinTicks;
   A.ticket = c->at<uint32_t>(L.ticket);
   A.classes = 0;
   A.fan_in = c->fan_in;

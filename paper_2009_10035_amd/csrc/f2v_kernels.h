@@ -87,7 +87,7 @@ struct EpochArgs {
   float lr, eps;
   int32_t strict_batch;     // >= 0: process only this batch, no waits
   int32_t strict_late;      // with strict_batch: 0 its whole and early units, 1 its late units
-  uint32_t spin_limit;      // bound on polls of one dependency wait
+  uint64_t spin_ticks;      // bound on one dependency wait, in ticks of the constant clock
   uint32_t* ticket;         // claim counters (kClaimStride words apart), or nullptr
   int32_t classes;          // > 0: waves claim groups from `classes` counters, else static
   int32_t fan_in;           // fan-in of the combining tree of split rows

@@ -57,9 +57,9 @@ struct WaveCounters {
 };
 
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
-// Bounded: after spin_limit polls (or once another wave has reported a
-// timeout) it sets the error word and returns.  Polls back off from 64 to 512
-// cycles of sleep.
+// Bounded: after spin_ticks of the device's constant clock (or once another
+// wave has reported a timeout) it sets the error word and returns.  Polls
+// back off from 64 to 1024 cycles of sleep.
 template <int U>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
@@ -68,6 +68,7 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
   for (int q = 0; q < U; ++q) any |= pend[q];
   if (!__any(any)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
+  const uint64_t t_begin = wall_clock64();
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
@@ -85,11 +86,13 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
     }
     if (!__any(any)) break;
     ++polls;
-    if (polls >= A.spin_limit) {
-      if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
-      break;
+    if ((polls & 63u) == 0) {
+      if (wall_clock64() - t_begin > A.spin_ticks) {
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+        break;
+      }
+      if (ld_coherent_u32(A.err) != 0) break;
     }
-    if ((polls & 255u) == 0 && ld_coherent_u32(A.err) != 0) break;
     if (polls < 8) __builtin_amdgcn_s_sleep(1);
     else if (polls < 32) __builtin_amdgcn_s_sleep(4);
     else __builtin_amdgcn_s_sleep(16);
@@ -340,17 +343,20 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
+  const uint64_t t_begin = wall_clock64();
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
     if (pend) pend = ld_coherent_u32(flag) == 0u;
     if (!__any(pend)) break;
     ++polls;
-    if (polls >= A.spin_limit) {
-      if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
-      break;
+    if ((polls & 63u) == 0) {
+      if (wall_clock64() - t_begin > A.spin_ticks) {
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+        break;
+      }
+      if (ld_coherent_u32(A.err) != 0) break;
     }
-    if ((polls & 255u) == 0 && ld_coherent_u32(A.err) != 0) break;
     if (polls < 8) __builtin_amdgcn_s_sleep(1);
     else if (polls < 32) __builtin_amdgcn_s_sleep(4);
     else __builtin_amdgcn_s_sleep(16);
