@@ -96,14 +96,14 @@ typedef struct {
     int32_t schedule;     /* f2v_schedule */
     int32_t chunk;        /* neighbours per work unit; rows of higher degree are
                              split into several units whose partial sums are
-                             combined in a fixed order.  0 = default (32). */
+                             combined in a fixed order.  0 = default (64). */
     uint64_t seed;        /* key of every random stream */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
- * eps = 1e-3, random partition, dataflow schedule, chunk 32, seed 0.
+ * eps = 1e-3, random partition, dataflow schedule, chunk 64, seed 0.
  * n, nnz and d must still be set. */
 void f2v_default_params(f2v_params *p);
 

@@ -19,7 +19,7 @@ using f2v::Variant;
 
 namespace {
 
-constexpr int kDefaultChunk = 32;
+constexpr int kDefaultChunk = 64;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocksPerCu = 6;

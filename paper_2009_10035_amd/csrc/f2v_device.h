@@ -256,6 +256,20 @@ __device__ __forceinline__ float row_broadcast(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150 + kSrc,
                                                              0xF, 0xF, false));
 }
+// row_broadcast with the source lane given as a value that folds to a
+// constant once the caller's loop is unrolled.
+__device__ __forceinline__ float row_broadcast_any(int src, float x) {
+  switch (src) {
+    case 0: return row_broadcast<0>(x);
+    case 1: return row_broadcast<1>(x);
+    case 2: return row_broadcast<2>(x);
+    case 3: return row_broadcast<3>(x);
+    case 4: return row_broadcast<4>(x);
+    case 5: return row_broadcast<5>(x);
+    case 6: return row_broadcast<6>(x);
+    default: return row_broadcast<7>(x);
+  }
+}
 // x of this lane plus x of the lane whose index differs by `kCtrl`'s pattern,
 // where the partner's value is `send` (selected per lane).
 template <int kCtrl>

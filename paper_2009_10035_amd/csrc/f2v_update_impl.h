@@ -42,10 +42,10 @@ struct LossShape {
   static constexpr int kStep = G * kIdxPerLane;
 };
 
-template <int G, int R>
+template <int G, int R, bool BF16>
 struct Unroll {
   // rows kept in flight per lane while their dot products are reduced
-  static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : 8);
+  static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : (BF16 && G == 64 ? 16 : 8));
 };
 
 // Diagnostic counters of one wave, kept in LDS (not registers, which the
@@ -167,6 +167,51 @@ struct TreeLoads {
   static constexpr int value = 4;
 };
 
+// Force coefficients of a batch of U entries from their per-lane partial dot
+// products (or squared distances); every lane of a group gets all U.
+template <int G, int kForce, int U>
+__device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq)[U], const bool (&rep)[U],
+                                            float (&cq)[U]) {
+  if constexpr (G >= 16 && U == 16) {
+    // two rounds of eight sums
+    uint32_t repmask = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
+    const int row = static_cast<int>(threadIdx.x & 7);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float dh[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dh[q] = dq[8 * h + q];
+      const float dl = group_sum8_scatter<G>(dh);
+      const float cl = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+      cq[8 * h + 0] = row_broadcast<0>(cl); cq[8 * h + 1] = row_broadcast<1>(cl);
+      cq[8 * h + 2] = row_broadcast<2>(cl); cq[8 * h + 3] = row_broadcast<3>(cl);
+      cq[8 * h + 4] = row_broadcast<4>(cl); cq[8 * h + 5] = row_broadcast<5>(cl);
+      cq[8 * h + 6] = row_broadcast<6>(cl); cq[8 * h + 7] = row_broadcast<7>(cl);
+    }
+  } else if constexpr (G >= 16 && U == 8) {
+    // the eight sums at once; lane l computes the coefficient of row l % 8
+    // and every lane reads the eight coefficients back
+    uint32_t repmask = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
+    const float dl = group_sum8_scatter<G>(dq);
+    const int row = static_cast<int>(threadIdx.x & 7);
+    const float cl = ((repmask >> row) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+    cq[0] = row_broadcast<0>(cl); cq[1] = row_broadcast<1>(cl);
+    cq[2] = row_broadcast<2>(cl); cq[3] = row_broadcast<3>(cl);
+    cq[4] = row_broadcast<4>(cl); cq[5] = row_broadcast<5>(cl);
+    cq[6] = row_broadcast<6>(cl); cq[7] = row_broadcast<7>(cl);
+  } else {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const float t = group_sum<G>(dq[q]);
+      cq[q] = rep[q] ? repulse_coef(kForce, t, A.eps) : attract_coef(kForce, t);
+    }
+  }
+}
+
 // One batch of up to U entries (`cnt` left from `ent`, in LDS) of one region
 // of a step: rows of the epoch-start buffer (kNext false: plain loads, no
 // wait) or of earlier batches (kNext: awaited, device-scope loads).  Adds each
@@ -190,6 +235,69 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     rep[q] = (e & kEntRepulsive) != 0u;
   }
   if (kNext && wait) wait_published<U>(A, vid, pend, wc);
+  if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
+    // bf16 rows kept packed (one dword per lane and row) and widened at each
+    // use, so that twice as many rows fit in the registers
+    const uint32_t* src32 = reinterpret_cast<const uint32_t*>(src);
+    uint32_t yr[U][R];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e0 = (r * G + l) * V;
+        if (vid[q] >= 0 && (FULL || e0 < A.d)) {
+          const uint32_t* p = src32 + (static_cast<int64_t>(vid[q]) * A.d + e0) / 2;
+          yr[q][r] = kNext ? ld_coherent_u32(p) : *p;
+        } else {
+          yr[q][r] = 0u;
+        }
+      }
+    // lane l of each row of 16 holds the coefficients of entries l % 8 and
+    // 8 + l % 8; each is broadcast where it is used
+    uint32_t repmask = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
+    const int row = static_cast<int>(threadIdx.x & 7);
+    float cl[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float dh[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float t[R][V];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          t[r][0] = __uint_as_float(yr[8 * h + q][r] << 16);
+          t[r][1] = __uint_as_float(yr[8 * h + q][r] & 0xffff0000u);
+        }
+        dh[q] = pair_partial<R, V>(kForce, a, t);
+      }
+      const float dl = group_sum8_scatter<G>(dh);
+      cl[h] = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (vid[q] >= 0) {
+        const float c = row_broadcast_any(q & 7, cl[q >> 3]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          // a fresh widening (not the dot product's): the packed dword is
+          // what stays live
+          uint32_t w = yr[q][r];
+          asm volatile("" : "+v"(w));
+          const float y0 = __uint_as_float(w << 16), y1 = __uint_as_float(w & 0xffff0000u);
+          if constexpr (kForce == kSigmoid) {
+            acc[r][0] = fmaf(c, y0, acc[r][0]);
+            acc[r][1] = fmaf(c, y1, acc[r][1]);
+          } else {
+            acc[r][0] = fmaf(c, a[r][0] - y0, acc[r][0]);
+            acc[r][1] = fmaf(c, a[r][1] - y1, acc[r][1]);
+          }
+        }
+      }
+    }
+    return;
+  }
   float y[U][R][V];
 #pragma unroll
   for (int q = 0; q < U; ++q) {
@@ -206,26 +314,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
 #pragma unroll
   for (int q = 0; q < U; ++q) dq[q] = pair_partial<R, V>(kForce, a, y[q]);
   float cq[U];
-  if constexpr (G >= 16 && U == 8) {
-    // the eight sums at once; lane l computes the coefficient of row l % 8
-    // and every lane reads the eight coefficients back
-    uint32_t repmask = 0;
-#pragma unroll
-    for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
-    const float dl = group_sum8_scatter<G>(dq);
-    const int row = static_cast<int>(threadIdx.x & 7);
-    const float cl = ((repmask >> row) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
-    cq[0] = row_broadcast<0>(cl); cq[1] = row_broadcast<1>(cl);
-    cq[2] = row_broadcast<2>(cl); cq[3] = row_broadcast<3>(cl);
-    cq[4] = row_broadcast<4>(cl); cq[5] = row_broadcast<5>(cl);
-    cq[6] = row_broadcast<6>(cl); cq[7] = row_broadcast<7>(cl);
-  } else {
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const float t = group_sum<G>(dq[q]);
-      cq[q] = rep[q] ? repulse_coef(kForce, t, A.eps) : attract_coef(kForce, t);
-    }
-  }
+  batch_coefs<G, kForce, U>(A, dq, rep, cq);
 #pragma unroll
   for (int q = 0; q < U; ++q) {
     if (vid[q] >= 0) {
@@ -259,7 +348,7 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
                                                 float (&acc)[R][V], WaveCounters& wc) {
   constexpr int K = ListShape<G>::kIdxPerLane;
   constexpr int kStep = ListShape<G>::kStep;
-  constexpr int U = Unroll<G, R>::value < kStep ? Unroll<G, R>::value : kStep;
+  constexpr int U = Unroll<G, R, BF16>::value < kStep ? Unroll<G, R, BF16>::value : kStep;
   const int lane = slot * G + l;
   const uint64_t group_mask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (slot * G));
   const uint64_t below = (1ull << lane) - 1ull;
@@ -565,7 +654,10 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
 }
 
 template <int G, int V, int R, bool BF16, bool FULL>
-__global__ __launch_bounds__(256) void k_update(EpochArgs A) {
+// Packed bf16 rows with one row per wave: sixteen rows in flight need more
+// registers than six waves per SIMD leave; the compiler is held to that
+// occupancy (a few values of the unit loop go to scratch).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && BF16 ? 6 : 1))) void k_update(EpochArgs A) {
   constexpr int S = 64 / G;
   // per-wave LDS for the reordered entries of a step (64 * kIdxPerLane words)
   __shared__ uint32_t order_lds[4][64 * ListShape<G>::kIdxPerLane];

@@ -1,6 +1,7 @@
 """Hash of the sources of the update kernel (its template, the device helpers
-and argument structs it includes, and its instance files), used to tell
-whether recorded hardware-counter measurements still describe it."""
+and argument structs it includes, its instance files, and the host code that
+chooses its launch and work-unit parameters), used to tell whether recorded
+hardware-counter measurements still describe it."""
 import hashlib
 import os
 
@@ -11,7 +12,8 @@ def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     names = [x for x in os.listdir(csrc)
-             if x in ("f2v_device.h", "f2v_kernels.h", "f2v_update_impl.h") or x.startswith("f2v_variants_")]
+             if x in ("f2v_device.h", "f2v_kernels.h", "f2v_update_impl.h", "f2v_api.cpp")
+             or x.startswith("f2v_variants")]
     for name in sorted(names):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
