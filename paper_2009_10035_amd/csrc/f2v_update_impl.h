@@ -28,10 +28,14 @@
 namespace f2v {
 
 // List entries fetched per step: kIdxPerLane per lane, kStep per lane group
-// (64 for G >= 4, so a default-size unit and its negatives take one step).
+// (64 for G >= 16, 32 for G = 8).  At most four per lane: with several rows
+// per wave every entry a lane holds is a register per row slot, and eight
+// per lane at G = 8 (d = 2) left three waves per SIMD instead of four (the
+// d = 2 layout update on 2M vertices: 1.38 ms with eight, 1.21 with four,
+// 1.89 with two).
 template <int G>
 struct ListShape {
-  static constexpr int kIdxPerLane = (64 / G) < 16 ? (64 / G) : 16;
+  static constexpr int kIdxPerLane = (64 / G) < 4 ? (64 / G) : 4;
   static constexpr int kStep = G * kIdxPerLane;
 };
 

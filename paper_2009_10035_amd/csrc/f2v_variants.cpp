@@ -14,8 +14,9 @@ extern const int kNumVariants_bf16_v4, kNumVariants_bf16_v2;
 // lanes hold no elements): fewer rows per wave means fewer rows of one wave
 // waiting on each other's dependencies, which matters more than lane use at
 // these widths (d = 2 layout epoch on 2M vertices: 20.3 ms with 1 lane per
-// row, 5.4 with 2, 3.0 with 4, 1.85 with 8, 2.2 with 16).  F2V_MIN_LANES (1..64,
-// power of two) overrides it.
+// row, 5.4 with 2, 3.0 with 4, 1.85 with 8, 2.2 with 16; with four list
+// entries per lane and step, 4.05 with 4, 1.75 with 8, 1.85 with 16).
+// F2V_MIN_LANES (1..64, power of two) overrides it.
 static int min_lanes() {
   static const int value = [] {
     int m = 8;
