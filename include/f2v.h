@@ -139,7 +139,9 @@ f2v_status f2v_loss(f2v_ctx *ctx, double out[3]);
 f2v_status f2v_sync_embedding(f2v_ctx *ctx);
 
 /* Synchronise the stream and report a device-side error raised since the
- * last check (F2V_E_TIMEOUT for an exceeded dependency wait). */
+ * last check (F2V_E_TIMEOUT for an exceeded dependency wait; f2v_last_error
+ * then names what the first wave to give up was waiting for: the vertex and
+ * its word, or the combining-tree node). */
 f2v_status f2v_check(f2v_ctx *ctx);
 
 /* Release the context (no device memory to free; the caller owns it). */
@@ -224,7 +226,9 @@ f2v_status f2v_server_flush(f2v_server *s);
 
 /* Non-blocking: report up to `cap` jobs that finished (done[i], status[i] =
  * F2V_OK or F2V_E_TIMEOUT), release their slots and budget.  A finished
- * job's embedding buffer holds its result (the FP32 master in the bf16 form). */
+ * job's embedding buffer holds its result (the FP32 master in the bf16 form).
+ * For a job that ended in F2V_E_TIMEOUT, f2v_server_last_error describes the
+ * wait that gave up, as f2v_check does. */
 f2v_status f2v_server_poll(f2v_server *s, uint64_t *done, int32_t *status, int32_t cap,
                            int32_t *n_done);
 

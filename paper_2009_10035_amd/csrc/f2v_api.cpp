@@ -86,7 +86,7 @@ Layout layout_of(const f2v_params& p) {
   L.hub_base = take(size_t(n) * 8);
   L.hub_cnt = take(size_t(L.hub_slot_cap) * 4);
   L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
-  L.err = take(4);
+  L.err = take(4 * f2v::kErrWords);
   L.csr_flag = take(4);
   L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
   L.scan_total = take(8);
@@ -194,6 +194,24 @@ float epoch_lr(const f2v_params& p, int32_t e) {
 }
 
 }  // namespace
+
+namespace f2v {
+// Message for a device error record (see kErrWords).
+std::string describe_timeout(const uint32_t* e) {
+  char buf[256];
+  if (e[2] == kWaitRow)
+    std::snprintf(buf, sizeof(buf),
+                  "a device dependency wait exceeded its bound: a unit of batch %u waited for vertex %u "
+                  "(its word was 0x%08x when the wait gave up)", e[3], e[1], e[4]);
+  else if (e[2] == kWaitFlag)
+    std::snprintf(buf, sizeof(buf),
+                  "a device dependency wait exceeded its bound: the late unit of a split row of batch %u waited "
+                  "for the flag of tree node %u (value %u when the wait gave up)", e[3], e[1], e[4]);
+  else
+    std::snprintf(buf, sizeof(buf), "a device dependency wait exceeded its bound");
+  return buf;
+}
+}  // namespace f2v
 
 extern "C" {
 
@@ -347,7 +365,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   uint32_t* errw = c->at<uint32_t>(L.err);
   const hipStream_t s = c->stream;
   if ((he = f2v::launch_fill_u32(flag, 0u, 1, s)) != hipSuccess ||
-      (he = f2v::launch_fill_u32(errw, 0u, 1, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(errw, 0u, f2v::kErrWords, s)) != hipSuccess ||
       (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
       (he = hipStreamSynchronize(s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("CSR check: ") + hipGetErrorString(he));
@@ -557,15 +575,16 @@ f2v_status f2v_vertex_trace(f2v_ctx* c, uint32_t* out) {
   return F2V_OK;
 }
 
+
 f2v_status f2v_check(f2v_ctx* c) {
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  uint32_t e = 0;
-  HIP_TRY(c, hipMemcpy(&e, c->at<uint32_t>(c->L.err), 4, hipMemcpyDeviceToHost));
-  if (e != 0) {
-    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, 1, c->stream));
+  uint32_t e[f2v::kErrWords] = {};
+  HIP_TRY(c, hipMemcpy(e, c->at<uint32_t>(c->L.err), sizeof(e), hipMemcpyDeviceToHost));
+  if (e[0] != 0) {
+    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, f2v::kErrWords, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return fail(&c->err, F2V_E_TIMEOUT, "a device dependency wait exceeded its bound");
+    return fail(&c->err, F2V_E_TIMEOUT, f2v::describe_timeout(e));
   }
   return F2V_OK;
 }

@@ -62,18 +62,15 @@ __device__ __forceinline__ uint32_t feistel_round(const Feistel& f, uint32_t r, 
   return philox(f.epoch, r, x, kTagPerm, f.seed).x & f.mask;
 }
 
-__device__ inline int32_t feistel_permute(const Feistel& f, int64_t p) {
-  uint64_t x = static_cast<uint64_t>(p);
-  do {
-    uint32_t hi = static_cast<uint32_t>(x >> f.half), lo = static_cast<uint32_t>(x) & f.mask;
-    for (uint32_t r = 0; r < kFeistelRounds; ++r) {
-      const uint32_t mixed = hi ^ feistel_round(f, r, lo);
-      hi = lo;
-      lo = mixed;
-    }
-    x = (static_cast<uint64_t>(hi) << f.half) | lo;
-  } while (x >= static_cast<uint64_t>(f.n));
-  return static_cast<int32_t>(x);
+// One pass of the network over the 2h-bit domain.
+__device__ inline uint64_t feistel_network(const Feistel& f, uint64_t x) {
+  uint32_t hi = static_cast<uint32_t>(x >> f.half), lo = static_cast<uint32_t>(x) & f.mask;
+  for (uint32_t r = 0; r < kFeistelRounds; ++r) {
+    const uint32_t mixed = hi ^ feistel_round(f, r, lo);
+    hi = lo;
+    lo = mixed;
+  }
+  return (static_cast<uint64_t>(hi) << f.half) | lo;
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,14 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
+// Device error record of a context: word 0 has bit 0 set once a dependency
+// wait exceeded its bound; the first wave to set it also records what it was
+// waiting for: [1] the vertex (row waits) or the tree node (flag waits),
+// [2] the kind (kWaitRow or kWaitFlag), [3] the batch of the waiting unit,
+// [4] the awaited word's value when the wait gave up.
+constexpr int kErrWords = 5;
+constexpr uint32_t kWaitRow = 1, kWaitFlag = 2;
+
 // Claim counters of the claiming schedules: at most kMaxClaimClasses, each
 // in its own 128-byte line.
 constexpr int kMaxClaimClasses = 1024;
@@ -78,7 +86,7 @@ struct EpochArgs {
   uint32_t* hub_cnt;        // tree node -> arrival counter; a row's first slot flags its
                             // early sum (all zero at the start of an epoch)
   float* hub_part;          // tree node -> partial sum [d]
-  uint32_t* err;            // device error word (bit 0: a wait exceeded its bound)
+  uint32_t* err;            // device error record [kErrWords] (word 0 bit 0: a wait exceeded its bound)
   uint64_t* wave_stats;     // optional [waves][kWaveStats] cycle counters (nullptr: off)
   uint32_t* trace;          // optional [n][2] wall-clock ticks: end of the last wait of the
                             // row's final unit, and its publication (nullptr: off)
@@ -178,8 +186,9 @@ hipError_t launch_negatives(int64_t n, int32_t b, int32_t s, uint64_t seed, uint
                             int32_t* negs, hipStream_t st);
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStream_t st);
 hipError_t launch_random_embedding(float* z, int64_t count, uint64_t seed, float scale, hipStream_t st);
-// Completion record of a server job: copies the job's device error word and
-// then `seq` into host-visible memory rec[0..1] (rec[0] written last).
+// Completion record of a server job: copies the job's device error record
+// into host-visible memory rec[1 .. kErrWords] and then `seq` into rec[0]
+// (written last).
 hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, const uint32_t* err, hipStream_t st);
 
 }  // namespace f2v

@@ -31,25 +31,48 @@ __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
   return deg <= chunk ? 1 : static_cast<int32_t>((deg + chunk - 1) / chunk);
 }
 
+// Random partition, position -> vertex, for positions t0, t0 + stride, ...
+// of [0, n): emit(position, vertex) for each.  Cycle walking takes a random
+// number of network passes per position (about 2 on average when n is just
+// above a power of four, 6 or more for some of a wave's 64 lanes).  Each round
+// of the loop applies one pass to every lane's current value, and a lane whose
+// walk has ended moves on to its next position, so short walks do not wait
+// for the longest one of the wave.
+constexpr int64_t kWalkPositions = 16;  // positions per thread at launch
+
+template <class Emit>
+__device__ __forceinline__ void walk_positions(const Feistel& f, int64_t n, int identity, int64_t t0,
+                                               int64_t stride, Emit emit) {
+  int64_t i = t0;
+  uint64_t x = static_cast<uint64_t>(i);
+  while (__any(i < n)) {
+    if (i < n) {
+      if (!identity) x = feistel_network(f, x);
+      if (x < static_cast<uint64_t>(n)) {
+        emit(i, static_cast<int32_t>(x));
+        i += stride;
+        x = static_cast<uint64_t>(i);
+      }
+    }
+  }
+}
+
 // K1: partition (position -> vertex, vertex -> batch word) and the shared
 // negatives of every batch.
 __global__ void k_setup_positions(SetupArgs A) {
   const Feistel f{A.seed, A.epoch, A.feistel_half, A.feistel_mask, A.n};
   const int64_t nneg = static_cast<int64_t>(A.nb) * A.s;
-  const int64_t total = A.n > nneg ? A.n : nneg;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (i < A.n) {
-      const int32_t v = A.identity ? static_cast<int32_t>(i) : feistel_permute(f, i);
-      A.perm[i] = v;
-      A.word[v] = static_cast<uint32_t>(i / A.b);
-      if (A.bat) A.bat[v] = static_cast<uint16_t>(i / A.b);
-    }
-    if (i < nneg) {
-      const uint32_t k = static_cast<uint32_t>(i / A.s), j = static_cast<uint32_t>(i % A.s);
-      const uint4 x = philox(A.epoch, k, j, kTagNeg, A.seed);
-      A.negs[i] = uniform_index(x.x, x.y, A.n);
-    }
+  const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  walk_positions(f, A.n, A.identity, t0, stride, [&](int64_t i, int32_t v) {
+    A.perm[i] = v;
+    A.word[v] = static_cast<uint32_t>(i / A.b);
+    if (A.bat) A.bat[v] = static_cast<uint16_t>(i / A.b);
+  });
+  for (int64_t q = t0; q < nneg; q += stride) {
+    const uint32_t k = static_cast<uint32_t>(q / A.s), j = static_cast<uint32_t>(q % A.s);
+    const uint4 r = philox(A.epoch, k, j, kTagNeg, A.seed);
+    A.negs[q] = uniform_index(r.x, r.y, A.n);
   }
 }
 
@@ -552,9 +575,8 @@ __global__ void k_loss_reduce(const double* part, int64_t n, double* out) {
 }
 
 __global__ void k_partition(int64_t n, Feistel f, int identity, int32_t* perm) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    perm[i] = identity ? static_cast<int32_t>(i) : feistel_permute(f, i);
+  walk_positions(f, n, identity, blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x,
+                 static_cast<int64_t>(gridDim.x) * blockDim.x, [&](int64_t i, int32_t v) { perm[i] = v; });
 }
 
 __global__ void k_negatives(int64_t n, int64_t count, int32_t s, uint64_t seed, uint32_t epoch,
@@ -590,7 +612,8 @@ __global__ void k_random_embedding(float* z, int64_t count, uint64_t seed, float
 
 __global__ void k_signal(uint32_t* rec, uint32_t seq, const uint32_t* err) {
   if (threadIdx.x == 0) {
-    __hip_atomic_store(rec + 1, *err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (int i = 0; i < kErrWords; ++i)
+      __hip_atomic_store(rec + 1 + i, err[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(rec, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
@@ -606,7 +629,9 @@ int grid_for(int64_t work, int threads) {
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
-  hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(a.n > nneg ? a.n : nneg, 256)), dim3(256), 0, st, a);
+  // one thread per kWalkPositions positions, or per negative if there are more
+  const int64_t walkers = (a.n + kWalkPositions - 1) / kWalkPositions;
+  hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(walkers > nneg ? walkers : nneg, 256)), dim3(256), 0, st, a);
   if (a.nsplit > 0) {
     hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 16, 256)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * (64 / kSortRowsPerWave), 256)), dim3(256), 0, st,
@@ -668,7 +693,8 @@ hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st) {
 hipError_t launch_partition(int64_t n, uint64_t seed, uint32_t epoch, int identity, int32_t* perm,
                             hipStream_t st) {
   const Feistel f = make_feistel(n, seed, epoch);
-  hipLaunchKernelGGL(k_partition, dim3(grid_for(n, 256)), dim3(256), 0, st, n, f, identity, perm);
+  hipLaunchKernelGGL(k_partition, dim3(grid_for((n + kWalkPositions - 1) / kWalkPositions, 256)), dim3(256), 0, st,
+                     n, f, identity, perm);
   return hipGetLastError();
 }
 

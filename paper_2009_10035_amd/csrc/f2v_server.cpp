@@ -27,9 +27,15 @@ namespace f2v {
 void ctx_set_record_events(f2v_ctx* c, bool on);
 hipStream_t ctx_stream(const f2v_ctx* c);
 const uint32_t* ctx_err_word(const f2v_ctx* c);
+std::string describe_timeout(const uint32_t* err);
 }  // namespace f2v
 
 namespace {
+
+// Words per slot of the completion records: the sequence number, then the
+// job's device error record.
+constexpr size_t kRecWords = 8;
+static_assert(1 + f2v::kErrWords <= kRecWords, "completion record too small");
 
 struct Job {
   uint64_t id = 0;
@@ -53,7 +59,7 @@ struct f2v_server {
   std::vector<hipStream_t> streams;
   std::vector<uint64_t> slot_job;    // 0 = free
   std::vector<hipEvent_t> fork_join; // per slot, for graph capture
-  uint32_t* host_rec = nullptr;      // pinned [slots][2]: seq, error word
+  uint32_t* host_rec = nullptr;      // pinned [slots][kRecWords]: seq, device error record
   std::unordered_map<uint64_t, Job> jobs;
   std::vector<uint64_t> pending;     // packed jobs waiting for f2v_server_flush
   std::deque<GraphRun> graphs;       // launched graphs not yet destroyed
@@ -83,7 +89,7 @@ f2v_status enqueue_run(f2v_server* s, Job& j) {
   }
   f2v_status st = f2v_sync_embedding(j.ctx);
   if (st != F2V_OK) return sfail(s, st, std::string("sync: ") + f2v_last_error(j.ctx));
-  SRV_HIP(s, f2v::launch_signal(s->host_rec + 2 * j.slot, j.seq, f2v::ctx_err_word(j.ctx),
+  SRV_HIP(s, f2v::launch_signal(s->host_rec + kRecWords * j.slot, j.seq, f2v::ctx_err_word(j.ctx),
                                 s->streams[j.slot]));
   return F2V_OK;
 }
@@ -132,10 +138,10 @@ f2v_status f2v_server_create(size_t hbm_budget, int32_t max_slots, f2v_server** 
     e = hipEventCreateWithFlags(&s->fork_join[i], hipEventDisableTiming);
     if (e != hipSuccess) return bail(e);
   }
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&s->host_rec), size_t(max_slots) * 2 * sizeof(uint32_t),
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&s->host_rec), size_t(max_slots) * kRecWords * sizeof(uint32_t),
                                hipHostMallocCoherent);
   if (e != hipSuccess) return bail(e);
-  std::memset(s->host_rec, 0, size_t(max_slots) * 2 * sizeof(uint32_t));
+  std::memset(s->host_rec, 0, size_t(max_slots) * kRecWords * sizeof(uint32_t));
   *out = s;
   return F2V_OK;
 }
@@ -248,11 +254,14 @@ f2v_status f2v_server_poll(f2v_server* s, uint64_t* done, int32_t* status, int32
     const uint64_t id = s->slot_job[slot];
     if (id == 0) continue;
     Job& j = s->jobs.at(id);
-    const uint32_t seq = __atomic_load_n(s->host_rec + 2 * slot, __ATOMIC_ACQUIRE);
+    const uint32_t seq = __atomic_load_n(s->host_rec + kRecWords * slot, __ATOMIC_ACQUIRE);
     if (seq != j.seq) continue;
-    const uint32_t errw = __atomic_load_n(s->host_rec + 2 * slot + 1, __ATOMIC_RELAXED);
+    uint32_t rec[f2v::kErrWords];
+    for (int i = 0; i < f2v::kErrWords; ++i)
+      rec[i] = __atomic_load_n(s->host_rec + kRecWords * slot + 1 + i, __ATOMIC_RELAXED);
     done[*n_done] = id;
-    status[*n_done] = errw != 0 ? F2V_E_TIMEOUT : F2V_OK;
+    status[*n_done] = rec[0] != 0 ? F2V_E_TIMEOUT : F2V_OK;
+    if (rec[0] != 0) s->err = "job " + std::to_string(id) + ": " + f2v::describe_timeout(rec);
     ++*n_done;
     release(s, j);
     s->jobs.erase(id);

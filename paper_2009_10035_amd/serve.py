@@ -145,6 +145,9 @@ class DeviceServer:
     def result(self, jid: int):
         return self.buffers[jid]["z"]
 
+    def last_error(self) -> str:
+        return self.lib.f2v_server_last_error(self.handle).decode(errors="replace")
+
     def release(self, jid: int) -> None:
         self.buffers.pop(jid, None)
 
@@ -206,6 +209,9 @@ class SimulatedServer:
     def result(self, jid):
         return None
 
+    def last_error(self) -> str:
+        return ""
+
     def release(self, jid) -> None:
         pass
 
@@ -261,7 +267,7 @@ def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pac
             records[job.request] = dict(arrival=job.arrival, admitted=t_admit, done=t_done,
                                         latency=t_done - job.arrival, status=STATUS.get(status, status),
                                         n=job.graph.n, nnz=job.graph.nnz, d=job.d, precision=job.precision,
-                                        updates=job.updates)
+                                        updates=job.updates, error=server.last_error() if status else "")
             if status == 0:
                 total_updates += job.updates
         if progress and clock() - last_progress > 5.0:

@@ -39,7 +39,7 @@ def test_each_result_same_alone_and_in_the_mix():
     srv = DeviceServer(hbm_budget=8 << 30, max_slots=6)
     mix = run_requests(jobs, srv, keep=[j.request for j in jobs])
     srv.close()
-    assert mix["jobs"] == len(jobs) and mix["failed"] == 0
+    assert mix["jobs"] == len(jobs) and mix["failed"] == 0, [r["error"] for r in mix["records"].values() if r["error"]]
     for j in jobs[:8]:
         alone_srv = DeviceServer(hbm_budget=8 << 30, max_slots=1)
         alone = run_requests([JobSpec(**{**j.__dict__, "arrival": 0.0})], alone_srv, keep=[j.request])
