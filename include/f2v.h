@@ -96,14 +96,15 @@ typedef struct {
     int32_t schedule;     /* f2v_schedule */
     int32_t chunk;        /* neighbours per work unit; rows of higher degree are
                              split into several units whose partial sums are
-                             combined in a fixed order.  0 = default (64). */
+                             combined in a fixed order.  0 = default: 64 for
+                             n >= 750000, else 32. */
     uint64_t seed;        /* key of every random stream */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
- * eps = 1e-3, random partition, dataflow schedule, chunk 64, seed 0.
+ * eps = 1e-3, random partition, dataflow schedule, chunk 0 (by size), seed 0.
  * n, nnz and d must still be set. */
 void f2v_default_params(f2v_params *p);
 
@@ -139,9 +140,10 @@ f2v_status f2v_loss(f2v_ctx *ctx, double out[3]);
 f2v_status f2v_sync_embedding(f2v_ctx *ctx);
 
 /* Synchronise the stream and report a device-side error raised since the
- * last check (F2V_E_TIMEOUT for an exceeded dependency wait; f2v_last_error
- * then names what the first wave to give up was waiting for: the vertex and
- * its word, or the combining-tree node). */
+ * last check (F2V_E_TIMEOUT for an exceeded dependency wait).  After such a
+ * wait, later epochs of the context do nothing until this check, so the
+ * failed epoch's vertex words are kept: f2v_last_error then gives how many
+ * vertices were never published and the earliest of them. */
 f2v_status f2v_check(f2v_ctx *ctx);
 
 /* Release the context (no device memory to free; the caller owns it). */
@@ -227,8 +229,8 @@ f2v_status f2v_server_flush(f2v_server *s);
 /* Non-blocking: report up to `cap` jobs that finished (done[i], status[i] =
  * F2V_OK or F2V_E_TIMEOUT), release their slots and budget.  A finished
  * job's embedding buffer holds its result (the FP32 master in the bf16 form).
- * For a job that ended in F2V_E_TIMEOUT, f2v_server_last_error describes the
- * wait that gave up, as f2v_check does. */
+ * For a job that ended in F2V_E_TIMEOUT, f2v_server_last_error gives the
+ * unpublished vertices of its failed epoch, as f2v_check does. */
 f2v_status f2v_server_poll(f2v_server *s, uint64_t *done, int32_t *status, int32_t cap,
                            int32_t *n_done);
 

@@ -19,7 +19,14 @@ using f2v::Variant;
 
 namespace {
 
-constexpr int kDefaultChunk = 64;
+// Default neighbours per work unit: 64 for graphs of at least kLargeGraph
+// vertices, 32 below.  A large epoch is bound by throughput, and longer units
+// leave fewer rows split into early units, a combining tree and a late unit
+// (sbm4m, degrees around 30: update 19.0 ms at 32, 15.0 at 64).  A small one
+// is bound by the latency of its chain of batches, which shorter units cut
+// (serving jobs of 500 to 500k vertices: 80 jobs/s at 32, 71 at 64).
+constexpr int kSmallChunk = 32, kLargeChunk = 64;
+constexpr int64_t kLargeGraph = 750000;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocksPerCu = 6;
@@ -34,14 +41,16 @@ thread_local std::string g_error;
 
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, dkey, order, negs, wreal,
-      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, csr_flag, scan_scratch,
+      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, csr_flag, init_rec, scan_scratch,
       scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket, total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int32_t chunk_of(const f2v_params& p) { return p.chunk > 0 ? p.chunk : kDefaultChunk; }
+int32_t chunk_of(const f2v_params& p) {
+  return p.chunk > 0 ? p.chunk : (p.n >= kLargeGraph ? kLargeChunk : kSmallChunk);
+}
 
 Layout layout_of(const f2v_params& p) {
   Layout L{};
@@ -88,6 +97,7 @@ Layout layout_of(const f2v_params& p) {
   L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
   L.err = take(4 * f2v::kErrWords);
   L.csr_flag = take(4);
+  L.init_rec = take(3 * 8);
   L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
   L.scan_total = take(8);
   L.split_total = take(8);
@@ -198,17 +208,15 @@ float epoch_lr(const f2v_params& p, int32_t e) {
 namespace f2v {
 // Message for a device error record (see kErrWords).
 std::string describe_timeout(const uint32_t* e) {
-  char buf[256];
-  if (e[2] == kWaitRow)
+  char buf[320];
+  if (e[1] != 0)
     std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound: a unit of batch %u waited for vertex %u "
-                  "(its word was 0x%08x when the wait gave up)", e[3], e[1], e[4]);
-  else if (e[2] == kWaitFlag)
-    std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound: the late unit of a split row of batch %u waited "
-                  "for the flag of tree node %u (value %u when the wait gave up)", e[3], e[1], e[4]);
+                  "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
+                  "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
   else
-    std::snprintf(buf, sizeof(buf), "a device dependency wait exceeded its bound");
+    std::snprintf(buf, sizeof(buf),
+                  "a device dependency wait exceeded its bound (every vertex was published; a split row's "
+                  "early-sum flag was the one awaited)");
   return buf;
 }
 }  // namespace f2v
@@ -228,7 +236,7 @@ void f2v_default_params(f2v_params* p) {
   p->total_epochs = 1;
   p->perm_mode = F2V_PERM_RANDOM;
   p->schedule = F2V_SCHED_DATAFLOW;
-  p->chunk = kDefaultChunk;
+  p->chunk = 0;
   p->seed = 0;
 }
 
@@ -284,7 +292,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   f2v_ctx* c = new (std::nothrow) f2v_ctx();
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "host allocation failed");
   c->p = *p;
-  if (c->p.chunk == 0) c->p.chunk = kDefaultChunk;
+  c->p.chunk = chunk_of(c->p);
   c->L = L;
   c->stream = static_cast<hipStream_t>(stream);
   c->rowptr = d_rowptr;
@@ -361,17 +369,30 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   for (hipEvent_t& e : c->ev)
     if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
 
+  // The CSR check and the split-row setup are issued together and read back
+  // with one synchronisation (on a busy device every round trip waits for
+  // other work).  The setup kernels read only rowptr[0..n] and write inside
+  // their own arrays, so they are safe on a CSR the check rejects.
   uint32_t* flag = c->at<uint32_t>(L.csr_flag);
   uint32_t* errw = c->at<uint32_t>(L.err);
   const hipStream_t s = c->stream;
   if ((he = f2v::launch_fill_u32(flag, 0u, 1, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(errw, 0u, f2v::kErrWords, s)) != hipSuccess ||
       (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
+      (he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
+                                 c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
+      (he = f2v::launch_split_ids(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.loss_part),
+                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.split_total),
+                                  c->at<int32_t>(L.split_ids), s)) != hipSuccess ||
+      (bf16 && (he = f2v::launch_to_bf16(d_z, c->bbuf[0], p->n * int64_t(p->d), s)) != hipSuccess) ||
+      (he = f2v::launch_init_record(flag, c->at<int64_t>(L.scan_total), c->at<int64_t>(L.split_total),
+                                    c->at<int64_t>(L.init_rec), s)) != hipSuccess)
+    return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
+  int64_t rec[3] = {0, 0, 0};
+  if ((he = hipMemcpyAsync(rec, c->at<int64_t>(L.init_rec), sizeof(rec), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (he = hipStreamSynchronize(s)) != hipSuccess)
-    return bail(F2V_E_HIP, std::string("CSR check: ") + hipGetErrorString(he));
-  uint32_t hflag = 0;
-  if ((he = hipMemcpy(&hflag, flag, 4, hipMemcpyDeviceToHost)) != hipSuccess)
-    return bail(F2V_E_HIP, std::string("CSR check copy: ") + hipGetErrorString(he));
+    return bail(F2V_E_HIP, std::string("init sync: ") + hipGetErrorString(he));
+  const uint32_t hflag = static_cast<uint32_t>(rec[0]);
   if (hflag != 0) {
     std::string m = "malformed CSR:";
     if (hflag & 1u) m += " rowptr[0] != 0;";
@@ -380,19 +401,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (hflag & 8u) m += " column index outside [0, n);";
     return bail(F2V_E_BAD_GRAPH, m);
   }
-  int64_t hub_total = 0, nsplit = 0;
-  if ((he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
-                                 c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
-      (he = f2v::launch_split_ids(d_rowptr, p->n, c->p.chunk, c->at<int64_t>(L.loss_part),
-                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.split_total),
-                                  c->at<int32_t>(L.split_ids), s)) != hipSuccess)
-    return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
-  if (bf16 && (he = f2v::launch_to_bf16(d_z, c->bbuf[0], p->n * int64_t(p->d), s)) != hipSuccess)
-    return bail(F2V_E_HIP, std::string("bf16 copy: ") + hipGetErrorString(he));
-  if ((he = hipStreamSynchronize(s)) != hipSuccess ||
-      (he = hipMemcpy(&hub_total, c->at<int64_t>(L.scan_total), 8, hipMemcpyDeviceToHost)) != hipSuccess ||
-      (he = hipMemcpy(&nsplit, c->at<int64_t>(L.split_total), 8, hipMemcpyDeviceToHost)) != hipSuccess)
-    return bail(F2V_E_HIP, std::string("init sync: ") + hipGetErrorString(he));
+  const int64_t hub_total = rec[1], nsplit = rec[2];
   if (hub_total > L.hub_slot_cap) return bail(F2V_E_INVALID_ARG, "split-row slots exceed the workspace bound");
   if (nsplit < 0 || nsplit > p->n) return bail(F2V_E_INVALID_ARG, "split-row count out of range");
   c->hub_total = hub_total;
@@ -449,6 +458,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.epoch = static_cast<uint32_t>(epoch);
   sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
   sa.sort = c->sort;
+  sa.err = c->at<uint32_t>(L.err);
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;
@@ -580,6 +590,8 @@ f2v_status f2v_check(f2v_ctx* c) {
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   uint32_t e[f2v::kErrWords] = {};
+  HIP_TRY(c, f2v::launch_postmortem(c->at<uint32_t>(c->L.word), c->p.n, c->at<uint32_t>(c->L.err), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpy(e, c->at<uint32_t>(c->L.err), sizeof(e), hipMemcpyDeviceToHost));
   if (e[0] != 0) {
     HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, f2v::kErrWords, c->stream));
@@ -680,6 +692,8 @@ namespace f2v {
 // Accessors for the server (f2v_server.cpp).
 void ctx_set_record_events(f2v_ctx* c, bool on) { c->record_events = on; }
 hipStream_t ctx_stream(const f2v_ctx* c) { return c->stream; }
-const uint32_t* ctx_err_word(const f2v_ctx* c) { return c->at<uint32_t>(c->L.err); }
+uint32_t* ctx_err_word(f2v_ctx* c) { return c->at<uint32_t>(c->L.err); }
+const uint32_t* ctx_vertex_words(const f2v_ctx* c) { return c->at<uint32_t>(c->L.word); }
+int64_t ctx_n(const f2v_ctx* c) { return c->p.n; }
 
 }  // namespace f2v

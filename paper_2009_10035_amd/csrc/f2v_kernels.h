@@ -11,12 +11,12 @@ namespace f2v {
 constexpr uint32_t kPublished = 0x80000000u;
 
 // Device error record of a context: word 0 has bit 0 set once a dependency
-// wait exceeded its bound; the first wave to set it also records what it was
-// waiting for: [1] the vertex (row waits) or the tree node (flag waits),
-// [2] the kind (kWaitRow or kWaitFlag), [3] the batch of the waiting unit,
-// [4] the awaited word's value when the wait gave up.
+// wait exceeded its bound.  Later epochs then do nothing (the update and the
+// partition kernels return at once), so the vertex words of the epoch that
+// failed are kept, and a post-mortem fills [1] the number of vertices never
+// published in it, [2] the earliest batch among them, [3] one such vertex of
+// that batch and [4] its word.
 constexpr int kErrWords = 5;
-constexpr uint32_t kWaitRow = 1, kWaitFlag = 2;
 
 // Claim counters of the claiming schedules: at most kMaxClaimClasses, each
 // in its own 128-byte line.
@@ -140,6 +140,7 @@ struct SetupArgs {
   int32_t feistel_half;
   uint32_t feistel_mask;
   int32_t sort;             // order each batch's rows by readiness
+  const uint32_t* err;      // the context's error record: set = do nothing
 };
 
 struct LossArgs {
@@ -179,6 +180,12 @@ hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int3
 hipError_t launch_split_ids(const int64_t* rowptr, int64_t n, int32_t chunk, int64_t* flags,
                             int64_t* scratch, int64_t* count, int32_t* split_ids, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st);
+// Gather the init results (CSR check flag, split-row tree slots, split-row
+// count) into rec[0..2] for one read-back.
+// Post-mortem of a failed epoch (see kErrWords): no-op unless err[0] is set.
+hipError_t launch_postmortem(const uint32_t* word, int64_t n, uint32_t* err, hipStream_t st);
+hipError_t launch_init_record(const uint32_t* flag, const int64_t* hub_total, const int64_t* nsplit, int64_t* rec,
+                              hipStream_t st);
 hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st);
 hipError_t launch_partition(int64_t n, uint64_t seed, uint32_t epoch, int identity, int32_t* perm,
                             hipStream_t st);
@@ -186,9 +193,10 @@ hipError_t launch_negatives(int64_t n, int32_t b, int32_t s, uint64_t seed, uint
                             int32_t* negs, hipStream_t st);
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStream_t st);
 hipError_t launch_random_embedding(float* z, int64_t count, uint64_t seed, float scale, hipStream_t st);
-// Completion record of a server job: copies the job's device error record
-// into host-visible memory rec[1 .. kErrWords] and then `seq` into rec[0]
-// (written last).
-hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, const uint32_t* err, hipStream_t st);
+// Completion record of a server job: the post-mortem if the job failed (see
+// kErrWords), then the job's device error record into host-visible memory
+// rec[1 .. kErrWords] and `seq` into rec[0] (written last).
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n,
+                         hipStream_t st);
 
 }  // namespace f2v

@@ -38,7 +38,17 @@ __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
 // of the loop applies one pass to every lane's current value, and a lane whose
 // walk has ended moves on to its next position, so short walks do not wait
 // for the longest one of the wave.
-constexpr int64_t kWalkPositions = 16;  // positions per thread at launch
+// Threads for a walk over n positions: up to kWalkPositions positions each,
+// but one per position until the device is full (a small partition is bound
+// by latency, not by the passes).
+constexpr int64_t kWalkPositions = 16;
+constexpr int64_t kWalkFill = 256 * 1024;
+
+__host__ __forceinline__ int64_t walk_threads(int64_t n) {
+  const int64_t spread = (n + kWalkPositions - 1) / kWalkPositions;
+  const int64_t fill = n < kWalkFill ? n : kWalkFill;
+  return spread > fill ? spread : fill;
+}
 
 template <class Emit>
 __device__ __forceinline__ void walk_positions(const Feistel& f, int64_t n, int identity, int64_t t0,
@@ -60,6 +70,7 @@ __device__ __forceinline__ void walk_positions(const Feistel& f, int64_t n, int 
 // K1: partition (position -> vertex, vertex -> batch word) and the shared
 // negatives of every batch.
 __global__ void k_setup_positions(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed: keep its words
   const Feistel f{A.seed, A.epoch, A.feistel_half, A.feistel_mask, A.n};
   const int64_t nneg = static_cast<int64_t>(A.nb) * A.s;
   const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -129,6 +140,7 @@ __device__ __forceinline__ int64_t reorder_list(const SetupArgs& A, int32_t k, i
 // time: rows of at most kSmallSplit entries are done by 16 lanes each, at
 // once; longer ones by the whole wave, one after the other.
 __global__ void k_split_lists(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, l16 = lane & 15;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -177,6 +189,7 @@ constexpr int kSortRowsPerWave = 8;
 // longer than kSortLateMax, or windows wider than kSortLateWindow, keep their
 // order.
 __global__ void k_sort_late(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6;
@@ -231,6 +244,7 @@ __global__ void k_sort_late(SetupArgs A) {
 // K1b: 16 lanes per position: the latest earlier batch among the row's
 // neighbours (the batch whose publication it will wait for last).
 __global__ void k_readiness(SetupArgs A, const int32_t* colidx) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t p = tid >> 4;
   const int l = static_cast<int>(tid & 15);
@@ -296,6 +310,7 @@ __device__ int64_t scan_positions(const SetupArgs& A, int64_t lo, int64_t hi, in
 // units of that kind, and the batch's counts of each kind.  Rows of one batch
 // are independent, so the order inside a batch changes no result.
 __global__ void k_batch_units(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
   __shared__ int32_t keys[kSortMax];
@@ -346,6 +361,7 @@ __device__ __forceinline__ int32_t early_home(int32_t k, int32_t window) {
 // and the early units it holds), the first ticket of the batch, of its second
 // part and of its early units, and the group count.
 __global__ void k_batch_starts(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
   // exclusive prefix of the early counts
@@ -407,6 +423,7 @@ __global__ void k_batch_starts(SetupArgs A) {
 // position; threads [n, n + 2*nb*slots) mark the padding tickets at the end of
 // each batch's two parts.
 __global__ void k_tickets(SetupArgs A) {
+  if (*A.err != 0u) return;  // an earlier epoch failed
   const int64_t pad_threads = 2 * static_cast<int64_t>(A.nb) * A.slots;
   const int64_t total = A.n + pad_threads;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
@@ -542,6 +559,14 @@ __global__ void k_split_scatter(const int64_t* rowptr, int64_t n, int32_t chunk,
     if (rowptr[i + 1] - rowptr[i] > chunk) split_ids[slot[i]] = static_cast<int32_t>(i);
 }
 
+__global__ void k_init_record(const uint32_t* flag, const int64_t* hub_total, const int64_t* nsplit, int64_t* rec) {
+  if (threadIdx.x == 0) {
+    rec[0] = *flag;
+    rec[1] = *hub_total;
+    rec[2] = *nsplit;
+  }
+}
+
 __global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t count) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -610,7 +635,42 @@ __global__ void k_random_embedding(float* z, int64_t count, uint64_t seed, float
   }
 }
 
-__global__ void k_signal(uint32_t* rec, uint32_t seq, const uint32_t* err) {
+// Vertices whose word never got the published bit in the failed epoch: one
+// block counts them and keeps the one of the earliest batch (lowest vertex).
+__device__ void postmortem(const uint32_t* word, int64_t n, uint32_t* err) {
+  __shared__ unsigned long long best;
+  __shared__ unsigned int count;
+  if (threadIdx.x == 0) {
+    best = ~0ull;
+    count = 0;
+  }
+  __syncthreads();
+  for (int64_t v = threadIdx.x; v < n; v += blockDim.x) {
+    const uint32_t w = word[v];
+    if ((w & kPublished) == 0u) {
+      atomicAdd(&count, 1u);
+      atomicMin(&best, (static_cast<unsigned long long>(w) << 32) | static_cast<uint32_t>(v));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    err[1] = count;
+    err[2] = count ? static_cast<uint32_t>(best >> 32) : 0u;
+    err[3] = count ? static_cast<uint32_t>(best) : 0u;
+    err[4] = count ? word[static_cast<uint32_t>(best)] : 0u;
+  }
+}
+
+__global__ void k_postmortem(const uint32_t* word, int64_t n, uint32_t* err) {
+  if (err[0] == 0u) return;
+  postmortem(word, n, err);
+}
+
+__global__ void k_signal(uint32_t* rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n) {
+  if (err[0] != 0u) {
+    postmortem(word, n, err);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     for (int i = 0; i < kErrWords; ++i)
       __hip_atomic_store(rec + 1 + i, err[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -629,8 +689,7 @@ int grid_for(int64_t work, int threads) {
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
-  // one thread per kWalkPositions positions, or per negative if there are more
-  const int64_t walkers = (a.n + kWalkPositions - 1) / kWalkPositions;
+  const int64_t walkers = walk_threads(a.n);
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(walkers > nneg ? walkers : nneg, 256)), dim3(256), 0, st, a);
   if (a.nsplit > 0) {
     hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 16, 256)), dim3(256), 0, st, a);
@@ -680,6 +739,12 @@ hipError_t launch_split_ids(const int64_t* rowptr, int64_t n, int32_t chunk, int
   return hipGetLastError();
 }
 
+hipError_t launch_init_record(const uint32_t* flag, const int64_t* hub_total, const int64_t* nsplit, int64_t* rec,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_init_record, dim3(1), dim3(64), 0, st, flag, hub_total, nsplit, rec);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(count, 256)), dim3(256), 0, st, src, dst, count);
   return hipGetLastError();
@@ -693,8 +758,7 @@ hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st) {
 hipError_t launch_partition(int64_t n, uint64_t seed, uint32_t epoch, int identity, int32_t* perm,
                             hipStream_t st) {
   const Feistel f = make_feistel(n, seed, epoch);
-  hipLaunchKernelGGL(k_partition, dim3(grid_for((n + kWalkPositions - 1) / kWalkPositions, 256)), dim3(256), 0, st,
-                     n, f, identity, perm);
+  hipLaunchKernelGGL(k_partition, dim3(grid_for(walk_threads(n), 256)), dim3(256), 0, st, n, f, identity, perm);
   return hipGetLastError();
 }
 
@@ -713,8 +777,14 @@ hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, const uint32_t* err, hipStream_t st) {
-  hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, st, host_rec, seq, err);
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_signal, dim3(1), dim3(256), 0, st, host_rec, seq, err, word, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_postmortem(const uint32_t* word, int64_t n, uint32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_postmortem, dim3(1), dim3(256), 0, st, word, n, err);
   return hipGetLastError();
 }
 

@@ -26,7 +26,9 @@
 namespace f2v {
 void ctx_set_record_events(f2v_ctx* c, bool on);
 hipStream_t ctx_stream(const f2v_ctx* c);
-const uint32_t* ctx_err_word(const f2v_ctx* c);
+uint32_t* ctx_err_word(f2v_ctx* c);
+const uint32_t* ctx_vertex_words(const f2v_ctx* c);
+int64_t ctx_n(const f2v_ctx* c);
 std::string describe_timeout(const uint32_t* err);
 }  // namespace f2v
 
@@ -90,7 +92,7 @@ f2v_status enqueue_run(f2v_server* s, Job& j) {
   f2v_status st = f2v_sync_embedding(j.ctx);
   if (st != F2V_OK) return sfail(s, st, std::string("sync: ") + f2v_last_error(j.ctx));
   SRV_HIP(s, f2v::launch_signal(s->host_rec + kRecWords * j.slot, j.seq, f2v::ctx_err_word(j.ctx),
-                                s->streams[j.slot]));
+                                f2v::ctx_vertex_words(j.ctx), f2v::ctx_n(j.ctx), s->streams[j.slot]));
   return F2V_OK;
 }
 

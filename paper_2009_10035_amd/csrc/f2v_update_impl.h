@@ -60,29 +60,13 @@ struct WaveCounters {
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
-// A wait gave up: the lowest lane with `mine` sets the error bit and, if it
-// is the first in the epoch, records what it waited for.
-__device__ __forceinline__ void report_timeout(const EpochArgs& A, bool mine, uint32_t id, uint32_t kind,
-                                               int32_t k, uint32_t value) {
-  const uint64_t m = __ballot(mine);
-  const uint32_t src = m ? static_cast<uint32_t>(__builtin_ctzll(m)) : 0u;
-  if ((threadIdx.x & 63u) == src) {
-    if (atomicOr(A.err, 1u) == 0u) {
-      A.err[1] = id;
-      A.err[2] = kind;
-      A.err[3] = static_cast<uint32_t>(k);
-      A.err[4] = value;
-    }
-  }
-}
-
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
 // Bounded: after spin_ticks of the device's constant clock (or once another
 // wave has reported a timeout) it sets the error word and returns.  Polls
 // back off from 64 to 1024 cycles of sleep.
 template <int U>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
-                                               bool (&pend)[U], int32_t k, WaveCounters& wc) {
+                                               bool (&pend)[U], WaveCounters& wc) {
   bool any = false;
 #pragma unroll
   for (int q = 0; q < U; ++q) any |= pend[q];
@@ -108,15 +92,7 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
     ++polls;
     if ((polls & 63u) == 0) {
       if (wall_clock64() - t_begin > A.spin_ticks) {
-        bool mine = false;
-        uint32_t id = 0;
-#pragma unroll
-        for (int q = 0; q < U; ++q)
-          if (pend[q] && !mine) {
-            mine = true;
-            id = static_cast<uint32_t>(vid[q]);
-          }
-        report_timeout(A, mine, id, kWaitRow, k, mine ? ld_coherent_u32(A.word + id) : 0u);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
@@ -246,7 +222,7 @@ __device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq
 // entry's force on the group's row `a` into acc, in entry order.
 template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool kNext, int U>
 __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint32_t* ent, int cnt, bool wait,
-                                                 int32_t k, int l, const float (&a)[R][V], float (&acc)[R][V],
+                                                 int l, const float (&a)[R][V], float (&acc)[R][V],
                                                  WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
   const T* src = static_cast<const T*>(kNext ? A.zn : A.zc);
@@ -262,7 +238,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait) wait_published<U>(A, vid, pend, k, wc);
+  if (kNext && wait) wait_published<U>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -444,10 +420,9 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
     // region 0: rows of the epoch-start buffer (no wait); region 1: rows of
     // earlier batches, each awaited just before it is loaded
     for (int jb = 0; __any(jb < ncur); jb += U)
-      accumulate_batch<G, V, R, BF16, FULL, kForce, false, U>(A, my_order + jb, ncur - jb, wait, k, l, a, acc, wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, false, U>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
     for (int jb = 0; __any(jb < nnext); jb += U)
-      accumulate_batch<G, V, R, BF16, FULL, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, k, l, a, acc,
-                                                             wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
     // the next step overwrites the order: every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -457,7 +432,7 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
 
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set.
 // Bounded like wait_published.
-__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t k, WaveCounters& wc) {
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
@@ -470,8 +445,7 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
     ++polls;
     if ((polls & 63u) == 0) {
       if (wall_clock64() - t_begin > A.spin_ticks) {
-        report_timeout(A, pend, pend ? static_cast<uint32_t>(flag - A.hub_cnt) : 0u, kWaitFlag, k,
-                       pend ? ld_coherent_u32(flag) : 0u);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
@@ -544,7 +518,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, w.k, wc);
+    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
@@ -697,6 +671,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
   const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   uint32_t* order = order_lds[threadIdx.x >> 6];
+  // an earlier epoch of this context gave up on a wait: leave its vertex
+  // words as they are for the post-mortem
+  if (*A.err != 0u) return;
   int gbeg, gend;
   bool wait;
   if (A.strict_batch >= 0) {

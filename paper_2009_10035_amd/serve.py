@@ -108,9 +108,18 @@ class DeviceServer:
         torch = self.torch
         p = job.params()
         nbytes = workspace_size(p)
+        # the CSR goes over in one copy (rowptr, then colidx at an 8-byte
+        # aligned offset): on a busy device every copy waits for other work
+        rp, ci = job.graph.rowptr, job.graph.colidx
+        off = (rp.nbytes + 255) // 256 * 256
+        host = np.empty(off + ci.nbytes, dtype=np.uint8)
+        host[:rp.nbytes] = rp.view(np.uint8)
+        host[off:] = ci.view(np.uint8)
+        csr = torch.from_numpy(host).to(self.device, non_blocking=False)
         bufs = dict(
-            rowptr=torch.from_numpy(job.graph.rowptr).to(self.device, non_blocking=False),
-            colidx=torch.from_numpy(job.graph.colidx).to(self.device, non_blocking=False),
+            csr=csr,
+            rowptr=csr[:rp.nbytes].view(torch.int64),
+            colidx=csr[off:].view(torch.int32),
             z=torch.empty((job.graph.n, job.d), dtype=torch.float32, device=self.device),
             ws=torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device),
         )

@@ -56,7 +56,7 @@ def good(**over):
 
 def test_defaults_and_workspace():
     p = good()
-    assert p.batch == 384 and p.s == 5 and abs(p.lr0 - 0.02) < 1e-9 and p.chunk == 64
+    assert p.batch == 384 and p.s == 5 and abs(p.lr0 - 0.02) < 1e-9 and p.chunk == 0
     w128 = f2v.workspace_size(p)
     w256 = f2v.workspace_size(good(d=256))
     assert w256 > w128 > 1000 * 128 * 4

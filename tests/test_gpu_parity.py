@@ -67,7 +67,7 @@ def test_er1k_one_epoch_from_shared_state():
 @pytest.mark.parametrize("maker,chunk", [
     (lambda: gg.erdos_renyi(3000, 12.0, 1), 0),
     (lambda: gg.star(3000), 0),
-    (lambda: gg.star(3000), 32),
+    (lambda: gg.star(3000), 64),
     (lambda: gg.chung_lu(20000, 2.1, 20.0, 3), 0),
     (lambda: gg.chung_lu(20000, 2.1, 20.0, 3), 16),
 ])
