@@ -63,6 +63,9 @@ def serve_bench(args) -> int:
     out = run_requests(jobs, srv, progress=log)
     srv.close()
     rec = list(out["records"].values())
+    for r in rec:
+        if r["error"]:
+            log(f"failed job (n={r['n']}, d={r['d']}, {r['precision']}): {r['error']}")
     line = {
         "metric": "p99 job latency (serving, 1 MI355X)",
         "value": out["p99"],
