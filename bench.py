@@ -64,8 +64,8 @@ def serve_bench(args) -> int:
     srv.close()
     rec = list(out["records"].values())
     for r in rec:
-        if r["error"]:
-            log(f"failed job (n={r['n']}, d={r['d']}, {r['precision']}): {r['error']}")
+        for e in r["retried"] + ([r["error"]] if r["error"] else []):
+            log(f"device error in a job (n={r['n']}, d={r['d']}, {r['precision']}): {e}")
     line = {
         "metric": "p99 job latency (serving, 1 MI355X)",
         "value": out["p99"],
@@ -84,7 +84,7 @@ def serve_bench(args) -> int:
                    "closed_loop_capacity_jobs_per_s": capacity},
         "p50_s": out["p50"], "p99_s": out["p99"], "mean_s": out["mean"],
         "updates_per_s": out["updates_per_s"], "makespan_s": out["makespan"],
-        "failed": out["failed"], "host_seconds": out["host_seconds"],
+        "failed": out["failed"], "retried": out["retried"], "host_seconds": out["host_seconds"],
         "mean_n": float(np.mean([r["n"] for r in rec])), "total_updates": out["updates"],
     }
     print(json.dumps(line), flush=True)

@@ -77,7 +77,8 @@ __global__ void k_setup_positions(SetupArgs A) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   walk_positions(f, A.n, A.identity, t0, stride, [&](int64_t i, int32_t v) {
     A.perm[i] = v;
-    A.word[v] = static_cast<uint32_t>(i / A.b);
+    // device-scope: the update kernel polls this word and publishes into it
+    st_coherent_u32(A.word + v, static_cast<uint32_t>(i / A.b));
     if (A.bat) A.bat[v] = static_cast<uint16_t>(i / A.b);
   });
   for (int64_t q = t0; q < nneg; q += stride) {
@@ -409,7 +410,7 @@ __global__ void k_batch_starts(SetupArgs A) {
     A.bstart[A.nb] = static_cast<int32_t>(carry);
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
   }
-  for (int i = threadIdx.x; i < kMaxClaimClasses; i += blockDim.x) A.ticket[i * kClaimStride] = 0u;
+  for (int i = threadIdx.x; i < kMaxClaimClasses; i += blockDim.x) st_coherent_u32(A.ticket + i * kClaimStride, 0u);
   __syncthreads();
   __threadfence_block();
   for (int64_t k = threadIdx.x; k < A.nb; k += blockDim.x) {
@@ -478,10 +479,13 @@ __global__ void k_tickets(SetupArgs A) {
   }
 }
 
+// Fill with device-scope stores: the words filled here (counters, flags,
+// error words) are next used by device-scope atomics and polls, so the reset
+// goes to the same place those act on, not into one XCD's L2.
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    p[i] = v;
+    st_coherent_u32(p + i, v);
 }
 
 // CSR validation: bit 0 rowptr[0] != 0, bit 1 decreasing rowptr, bit 2

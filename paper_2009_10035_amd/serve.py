@@ -229,10 +229,14 @@ class SimulatedServer:
 
 
 def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pack_max_n: int = 50_000,
-                 z_seed: int = 12345, keep=None, idle_sleep: float = 50e-6, progress=None) -> dict:
+                 z_seed: int = 12345, keep=None, idle_sleep: float = 50e-6, progress=None,
+                 max_retries: int = 1) -> dict:
     """Serve `jobs` (sorted by arrival) on `server`; returns latency and
     throughput figures and the per-job records.  `keep`: request ids whose
-    results are copied to host memory (returned in 'results')."""
+    results are copied to host memory (returned in 'results').  A job that
+    ends in a device error is run again from its start, up to `max_retries`
+    times (every run of a job computes the same bits); its record keeps the
+    errors of the failed runs in 'retried'."""
     jobs = sorted(jobs, key=lambda j: j.arrival)
     t0 = clock()
     pending = collections.deque(jobs)
@@ -241,6 +245,7 @@ def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pac
     records = {}
     results = {}
     keep = set(keep or ())
+    retried = collections.defaultdict(list)   # request -> errors of its failed runs
     total_updates = 0
     last_progress = t0
     host = collections.Counter()   # host seconds per phase of the loop
@@ -270,13 +275,19 @@ def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pac
         for jid, status in finished:
             job, t_admit = inflight.pop(jid)
             t_done = clock() - t0
+            if status and len(retried[job.request]) < max_retries:
+                retried[job.request].append(server.last_error())
+                server.release(jid)
+                queue.appendleft(job)
+                continue
             if job.request in keep:
                 results[job.request] = server.result(jid).cpu().numpy().copy()
             server.release(jid)
             records[job.request] = dict(arrival=job.arrival, admitted=t_admit, done=t_done,
                                         latency=t_done - job.arrival, status=STATUS.get(status, status),
                                         n=job.graph.n, nnz=job.graph.nnz, d=job.d, precision=job.precision,
-                                        updates=job.updates, error=server.last_error() if status else "")
+                                        updates=job.updates, error=server.last_error() if status else "",
+                                        retried=list(retried[job.request]))
             if status == 0:
                 total_updates += job.updates
         if progress and clock() - last_progress > 5.0:
@@ -289,6 +300,7 @@ def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pac
     makespan = clock() - t0
     lat = np.array([r["latency"] for r in records.values()])
     return dict(jobs=len(records), failed=sum(r["status"] != "F2V_OK" for r in records.values()),
+                retried=sum(len(v) for v in retried.values()),
                 p50=float(np.percentile(lat, 50)) if len(lat) else 0.0,
                 p99=float(np.percentile(lat, 99)) if len(lat) else 0.0,
                 mean=float(lat.mean()) if len(lat) else 0.0, makespan=makespan,

@@ -62,3 +62,44 @@ def test_continuous_batching_admits_arrivals_while_others_run():
     overlaps = sum(1 for a, b in zip(recs, recs[1:]) if b["admitted"] < a["done"])
     assert overlaps > 10                     # jobs were admitted while others were running
     assert srv.max_active > 1
+
+
+class FlakyServer(SimulatedServer):
+    """Reports a device error for the first run of the listed requests."""
+
+    def __init__(self, fail_once, **kw):
+        super().__init__(**kw)
+        self.fail_once = set(fail_once)
+        self.req_of = {}
+        self.bad = set()
+
+    def submit(self, job, z_seed, pack):
+        jid = super().submit(job, z_seed, pack)
+        self.req_of[jid] = job.request
+        if job.request in self.fail_once:
+            self.fail_once.discard(job.request)
+            self.bad.add(jid)
+        return jid
+
+    def poll(self):
+        return [(jid, 6 if jid in self.bad else st) for jid, st in super().poll()]
+
+    def last_error(self) -> str:
+        return "a device dependency wait exceeded its bound"
+
+
+def test_a_failed_job_is_run_again_once():
+    clock = FakeClock()
+    jobs = small_jobs(40, rate=50.0)
+    srv = FlakyServer([3, 17], hbm_budget=10**12, max_slots=4, rate=2e6, clock=clock)
+    out = run_requests(jobs, srv, clock=clock, sleep=clock.sleep)
+    assert out["jobs"] == 40 and out["failed"] == 0 and out["retried"] == 2
+    for r in (3, 17):
+        rec = out["records"][r]
+        assert rec["status"] == "F2V_OK" and len(rec["retried"]) == 1
+        assert rec["latency"] >= 2 * jobs[r].updates / 2e6 - 1e-9   # both runs
+    assert all(not out["records"][j.request]["retried"] for j in jobs if j.request not in (3, 17))
+    # with no retries allowed the failure is reported
+    srv = FlakyServer([5], hbm_budget=10**12, max_slots=4, rate=2e6, clock=clock)
+    out = run_requests(jobs[:10], srv, clock=clock, sleep=clock.sleep, max_retries=0)
+    assert out["failed"] == 1 and out["records"][5]["status"] == "F2V_E_TIMEOUT"
