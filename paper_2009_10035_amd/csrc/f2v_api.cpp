@@ -31,10 +31,12 @@ constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocksPerCu = 6;
 constexpr int64_t kDynamicLookahead = 8;
-// Bound on one dependency wait: 10 s of the device's 100 MHz constant clock.
-// Waits end long before it unless the epoch cannot complete; concurrent jobs
-// can slow a wait down by far more than any poll count would allow for.
-constexpr uint64_t kSpinTicks = 1000000000ull;
+// Bound on one dependency wait: 250 ms of the device's 100 MHz constant
+// clock.  A unit waits only for the few batches in flight before its own, so
+// a wait cannot outlast its epoch (15 ms for the largest workload measured
+// here); one that reaches the bound means the epoch cannot complete, and the
+// sooner that is reported, the sooner a server can run the job again.
+constexpr uint64_t kSpinTicks = 25000000ull;
 constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
@@ -215,8 +217,8 @@ std::string describe_timeout(const uint32_t* e) {
                   "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
   else
     std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound (every vertex was published; a split row's "
-                  "early-sum flag was the one awaited)");
+                  "a device dependency wait exceeded its bound (after it gave up, every vertex of the epoch "
+                  "was published)");
   return buf;
 }
 }  // namespace f2v
