@@ -179,6 +179,10 @@ struct f2v_ctx {
   int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
   int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
   int32_t late_window = 24;   // batches whose neighbours a split row takes last (F2V_LATE_WINDOW)
+  // Failure drills, forced from the host (F2V_HOLD_VERTEX, F2V_WAIT_BOUND_US):
+  // a vertex whose publication is withheld, and the wait bound.
+  int32_t hold = -1;
+  uint64_t spin_ticks = kSpinTicks;
   int32_t claim_classes = 0;  // dataflow: 0 static round robin, else claim classes (F2V_CLAIM_CLASSES)
   int64_t nsplit = 0;         // rows of degree above chunk
   int64_t hub_total = 0;      // combining-tree slots of all split rows
@@ -352,6 +356,14 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     const int x = std::atoi(env);
     if (x >= 0 && x <= (1 << 20)) c->late_window = x;
   }
+  if (const char* env = std::getenv("F2V_HOLD_VERTEX")) {
+    const long long x = std::atoll(env);
+    if (x >= 0 && x < p->n) c->hold = static_cast<int32_t>(x);
+  }
+  if (const char* env = std::getenv("F2V_WAIT_BOUND_US")) {
+    const long long x = std::atoll(env);
+    if (x >= 1000 && x <= 100000000) c->spin_ticks = static_cast<uint64_t>(x) * 100u;  // 100 MHz clock
+  }
   {
     // The dynamic schedule (jobs sharing the device) gets one wave per group
     // of about kDynamicLookahead batches, at most the occupancy limit: a
@@ -498,7 +510,8 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.force = p.force;
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
-  A.spin_ticks = kSpinTicks;
+  A.spin_ticks = c->spin_ticks;
+  A.hold = c->hold;
   A.ticket = c->at<uint32_t>(L.ticket);
   A.classes = 0;
   A.fan_in = c->fan_in;

@@ -100,6 +100,8 @@ struct EpochArgs {
   int32_t classes;          // > 0: waves claim groups from `classes` counters, else static
   int32_t fan_in;           // fan-in of the combining tree of split rows
   int32_t late_window;      // batches before a unit's own whose rows are taken last
+  int32_t hold;             // >= 0: this vertex's row is written but never published (a
+                            // host-forced stall, to exercise the wait bound); -1: none
 };
 
 // Prologue of an epoch (random partition, negatives, split-row lists, work

@@ -645,7 +645,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
     }
   }
   drain_memory();
-  if (finish && l == 0) st_coherent_u32(A.word + u, static_cast<uint32_t>(w.k) | kPublished);
+  if (finish && l == 0 && u != A.hold) st_coherent_u32(A.word + u, static_cast<uint32_t>(w.k) | kPublished);
   if (A.trace && finish && l == 0) {
     A.trace[2 * static_cast<int64_t>(u)] = static_cast<uint32_t>(wc.last_wait_end);
     A.trace[2 * static_cast<int64_t>(u) + 1] = static_cast<uint32_t>(wall_clock64());

@@ -1,0 +1,68 @@
+"""Failure detection on the device, forced from the host (no kernel faults
+or hangs: every wait is bounded).  A vertex whose publication is withheld
+(F2V_HOLD_VERTEX) makes the rows that depend on it wait until the wait bound
+(F2V_WAIT_BOUND_US, short here): the epoch reports F2V_E_TIMEOUT with a
+post-mortem naming the vertex, later epochs do nothing until the check, and
+the server reports the job after running it once more."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2009_10035_amd as f2v
+from paper_2009_10035_amd._binding import F2VError
+from paper_2009_10035_amd.serve import DeviceServer, JobSpec, run_requests
+from gpu_helpers import device_graph, lib_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def held_case():
+    g = gg.erdos_renyi(3000, 12.0, 1)
+    p = dict(d=32, batch=128, s=5, force="sigmoid", lr0=0.02, seed=11)
+    # the vertex at position 0 of epoch 0 is in batch 0: its neighbours in
+    # later batches wait for its row
+    v = int(oracle.partition(g.n, p["seed"], 0)[0])
+    assert g.rowptr[v + 1] > g.rowptr[v]
+    return g, p, v
+
+
+@pytest.mark.parametrize("schedule", ["dataflow", "dynamic"])
+def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
+    g, p, v = held_case()
+    monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
+    monkeypatch.setenv("F2V_WAIT_BOUND_US", "20000")
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(gg.init_embedding(g.n, p["d"], 3), dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p, total_epochs=3, schedule=schedule))
+    tr.epoch(0)
+    tr.epoch(1)   # does nothing: epoch 0 failed
+    with pytest.raises(F2VError) as ei:
+        tr.check()
+    assert ei.value.name == "F2V_E_TIMEOUT"
+    msg = str(ei.value)
+    assert "1 vertices were never published" in msg and f"vertex {v} of batch 0" in msg, msg
+    tr.check()    # the error was reported once
+    tr.close()
+
+
+def test_server_runs_a_stalled_job_again_and_reports_it(monkeypatch):
+    g, p, v = held_case()
+    monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
+    monkeypatch.setenv("F2V_WAIT_BOUND_US", "20000")
+    job = JobSpec(request=0, arrival=0.0, graph=g, d=p["d"], precision="fp32", force="sigmoid", epochs=2,
+                  seed=p["seed"], batch=p["batch"], s=p["s"], lr0=p["lr0"])
+    srv = DeviceServer(hbm_budget=1 << 30, max_slots=2)
+    out = run_requests([job], srv)
+    srv.close()
+    rec = out["records"][0]
+    assert out["failed"] == 1 and out["retried"] == 1 and rec["status"] == "F2V_E_TIMEOUT"
+    for m in rec["retried"] + [rec["error"]]:
+        assert f"vertex {v} of batch 0" in m, m
