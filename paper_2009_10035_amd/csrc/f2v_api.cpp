@@ -30,7 +30,9 @@ constexpr int64_t kLargeGraph = 750000;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocksPerCu = 6;
-constexpr int64_t kDynamicLookahead = 8;
+// Batches of work units one dynamic-schedule grid covers: 4 served 81 jobs/s
+// in closed loop (300 jobs, 16 slots), against 77 at 8, 78 at 2 and 70 at 1.
+constexpr int64_t kDynamicLookahead = 4;
 // Bound on one dependency wait: 250 ms of the device's 100 MHz constant
 // clock.  A unit waits only for the few batches in flight before its own, so
 // a wait cannot outlast its epoch (15 ms for the largest workload measured
