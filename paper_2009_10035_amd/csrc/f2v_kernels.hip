@@ -31,13 +31,6 @@ __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
   return deg <= chunk ? 1 : static_cast<int32_t>((deg + chunk - 1) / chunk);
 }
 
-// Random partition, position -> vertex, for positions t0, t0 + stride, ...
-// of [0, n): emit(position, vertex) for each.  Cycle walking takes a random
-// number of network passes per position (about 2 on average when n is just
-// above a power of four, 6 or more for some of a wave's 64 lanes).  Each round
-// of the loop applies one pass to every lane's current value, and a lane whose
-// walk has ended moves on to its next position, so short walks do not wait
-// for the longest one of the wave.
 // Threads for a walk over n positions: up to kWalkPositions positions each,
 // but one per position until the device is full (a small partition is bound
 // by latency, not by the passes).
@@ -50,6 +43,13 @@ __host__ __forceinline__ int64_t walk_threads(int64_t n) {
   return spread > fill ? spread : fill;
 }
 
+// Random partition, position -> vertex, for positions t0, t0 + stride, ...
+// of [0, n): emit(position, vertex) for each.  Cycle walking takes a random
+// number of network passes per position (about 2 on average when n is just
+// above a power of four, 6 or more for some of a wave's 64 lanes).  Each round
+// of the loop applies one pass to every lane's current value, and a lane whose
+// walk has ended moves on to its next position, so short walks do not wait
+// for the longest one of the wave.
 template <class Emit>
 __device__ __forceinline__ void walk_positions(const Feistel& f, int64_t n, int identity, int64_t t0,
                                                int64_t stride, Emit emit) {
