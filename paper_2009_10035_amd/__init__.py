@@ -63,9 +63,31 @@ class Trainer:
     def epoch(self, e: int) -> None:
         check(self.lib.f2v_epoch(self.ctx, int(e)), self.ctx)
 
-    def run(self, epochs: int, first: int = 0) -> None:
+    def run(self, epochs: int, first: int = 0, log=None, loss_every: int = 0) -> None:
+        """Epochs first .. first + epochs - 1.  With `log` (a writable text
+        file), one JSON line per epoch: its device times (update kernel and
+        whole epoch, ms), edge+negative updates per second, algorithmic GB/s
+        of the update and its fraction of the 8 TB/s HBM peak, and every
+        `loss_every` epochs the Eq. 2 loss (total, attractive, repulsive;
+        this adds a pass over the graph)."""
+        import json
+        from .roofline import algorithmic_bytes
+        p = self.params
+        precision = "bf16" if p.precision == 1 else "fp32"
+        nbytes = algorithmic_bytes(p.n, p.nnz, p.d, p.batch, p.s, precision)
+        updates = p.nnz + p.n * p.s
         for e in range(first, first + epochs):
             self.epoch(e)
+            if log is None:
+                continue
+            upd_ms, ep_ms = self.last_epoch_ms()
+            rec = {"epoch": e, "update_ms": upd_ms, "epoch_ms": ep_ms,
+                   "updates_per_s": updates / (ep_ms * 1e-3) if ep_ms > 0 else None,
+                   "update_gbs": nbytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else None}
+            rec["frac_of_hbm_peak"] = rec["update_gbs"] / 8000.0 if rec["update_gbs"] else None
+            if loss_every and (e - first + 1) % loss_every == 0:
+                rec["loss"], rec["loss_attractive"], rec["loss_repulsive"] = self.loss()
+            log.write(json.dumps(rec) + "\n")
 
     def loss(self):
         out = (ctypes.c_double * 3)()
