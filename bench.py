@@ -155,7 +155,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the update is measured on one GPU; --gpus must be 1"}))
         log("only --gpus 1 is supported: the update is measured on one MI355X")
         return 2
     if args.workload == "serve":

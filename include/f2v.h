@@ -58,7 +58,7 @@ typedef enum {
     F2V_E_TIMEOUT = 6,     /* a device-side dependency wait exceeded its bound;
                               the embedding is not valid after this */
     F2V_E_BUSY = 7,        /* serving: no free slot or memory for the job */
-    F2V_E_UNSUPPORTED = 8  /* valid request this build does not implement */
+    F2V_E_UNSUPPORTED = 8  /* valid request the library does not implement */
 } f2v_status;
 
 typedef enum { F2V_FORCE_SIGMOID = 0, F2V_FORCE_STUDENT_T = 1 } f2v_force;
