@@ -63,6 +63,17 @@ def test_defaults_and_workspace():
     assert f2v.workspace_size(good(precision="bf16")) < w128 * 2
 
 
+def test_default_chunk_follows_graph_size():
+    # chunk 0 picks 32 below 750k vertices and 64 from there on: the
+    # workspace bound of chunk 0 equals that of the explicit choice
+    for n, chunk in ((10_000, 32), (749_999, 32), (750_000, 64), (2_000_000, 64)):
+        nnz = 20 * n
+        auto = f2v.workspace_size(f2v.make_params(n, nnz, 128))
+        assert auto == f2v.workspace_size(f2v.make_params(n, nnz, 128, chunk=chunk)), (n, chunk)
+        other = 64 if chunk == 32 else 32
+        assert auto != f2v.workspace_size(f2v.make_params(n, nnz, 128, chunk=other)), (n, other)
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("n", 0, "F2V_E_INVALID_ARG"), ("n", 2**29, "F2V_E_INVALID_ARG"), ("d", 0, "F2V_E_INVALID_ARG"),
     ("d", 1025, "F2V_E_INVALID_ARG"), ("d", 130, "F2V_E_UNSUPPORTED"), ("d", 65, "F2V_E_UNSUPPORTED"),
