@@ -88,7 +88,8 @@ def serve_bench(args) -> int:
         "mean_n": float(np.mean([r["n"] for r in rec])), "total_updates": out["updates"],
     }
     print(json.dumps(line), flush=True)
-    return 0 if out["failed"] == 0 else 1
+    # a job that had to be run again counts as a failure of the run
+    return 0 if out["failed"] == 0 and out["retried"] == 0 else 1
 
 
 from paper_2009_10035_amd.roofline import algorithmic_bytes  # noqa: E402
@@ -113,25 +114,145 @@ def recorded_traffic(workload: str, precision: str):
     return rec["traffic_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's, from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(g, Z, op, nb, seconds_target, threads):
+    """The FP64 oracle over the first batches of epoch 0, growing the sample
+    until it takes about seconds_target; returns (pairs, seconds, batches)."""
+    import oracle
+    batches = 8
+    while True:
+        t0 = time.perf_counter()
+        _, pairs = oracle.epoch(g, Z, 0, op, return_pairs=True, batches=(0, min(batches, nb)), threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= seconds_target or batches >= nb:
+            return pairs, dt, min(batches, nb)
+        batches = min(nb, int(batches * max(2.0, 1.2 * seconds_target / max(dt, 1e-3))))
+
+
 def cpu_baseline(g, Z0, p, seconds_target: float = 12.0) -> dict:
-    """Time the FP64 oracle (as it stands) on the host over the first batches
-    of epoch 0, growing the sample until it takes about `seconds_target`."""
+    """Time the FP64 oracle (as it stands) on the host cores over the first
+    batches of epoch 0, growing the sample until it takes about
+    `seconds_target`; then on one thread over a sample a quarter as long."""
     import oracle
     op = oracle.OracleParams.from_dict(p)
     Z = np.asarray(Z0, dtype=np.float64)
     nb = (g.n + op.batch - 1) // op.batch
-    batches = 8
-    while True:
-        t0 = time.perf_counter()
-        _, pairs = oracle.epoch(g, Z, 0, op, return_pairs=True, batches=(0, min(batches, nb)))
-        dt = time.perf_counter() - t0
-        if dt >= seconds_target or batches >= nb:
-            break
-        batches = min(nb, int(batches * max(2.0, 1.2 * seconds_target / max(dt, 1e-3))))
-        log(f"cpu baseline: growing sample to {batches} batches")
+    pairs, dt, batches = time_oracle(g, Z, op, nb, seconds_target, 0)
+    pairs1, dt1, batches1 = time_oracle(g, Z, op, nb, seconds_target / 4, 1)
     return {"value": pairs / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {min(batches, nb)} of {nb} batches of epoch 0 ({pairs} pair updates, "
-                      f"{dt:.1f} s, FP64, OpenMP over the batch's vertices)"}
+            "cpu_model": cpu_model(), "single_thread_value": pairs1 / dt1,
+            "sample": f"first {batches} of {nb} batches of epoch 0 ({pairs} pair updates, "
+                      f"{dt:.1f} s, FP64, OpenMP over the batch's vertices); single thread: first "
+                      f"{batches1} batches ({pairs1} pair updates, {dt1:.1f} s)"}
+
+
+def measure(name: str, args, precision=None, schedule="dataflow", warmup=1, steps=5):
+    """Run `warmup` + `steps` epochs of a workload on the device; returns the
+    graph, the start state, the parameters and the figures of the timed
+    epochs (wall-clock throughput; the update kernel's average duration from
+    HIP events on the library's stream, in a second pass, and its roofline
+    fraction)."""
+    import torch
+    import graphgen as gg
+    import paper_2009_10035_amd as f2v
+
+    t0 = time.perf_counter()
+    g, p = gg.workload(name)
+    if precision:
+        p["precision"] = precision
+    log(f"graph {name}: n={g.n} nnz={g.nnz} max degree={int(g.degrees().max())} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
+    dev = torch.device("cuda:0")
+    rowptr = torch.from_numpy(g.rowptr).to(dev)
+    colidx = torch.from_numpy(g.colidx).to(dev)
+    z = torch.from_numpy(Z0).to(dev)
+    params = f2v.make_params(g.n, g.nnz, p["d"], batch=p["batch"], s=p["s"], force=p["force"],
+                             precision=p["precision"], lr0=p["lr0"], lr_schedule=p["lr_schedule"],
+                             total_epochs=max(p["total_epochs"], warmup + 2 * steps),
+                             schedule=schedule, chunk=args.chunk or None, seed=p["seed"])
+    tr = f2v.Trainer(rowptr, colidx, z, params)
+    for e in range(warmup):
+        tr.epoch(e)
+    tr.check()
+    log(f"{name}: warm-up done ({warmup} epochs)")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for e in range(warmup, warmup + steps):
+        tr.epoch(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    tr.check()
+    # per-launch device time of the update kernel, from HIP events on the
+    # library's stream (separate pass so the timed loop has no host syncs)
+    upd_ms = []
+    for e in range(warmup + steps, warmup + 2 * steps):
+        tr.epoch(e)
+        upd_ms.append(tr.last_epoch_ms())
+    tr.check()
+    health = tr.health()
+    loss = tr.loss()
+    tr.close()
+    del rowptr, colidx, z
+    torch.cuda.empty_cache()
+    log(f"{name}: timed {steps} epochs in {wall * 1e3:.2f} ms; loss {loss[0]:.6g}; health {health}")
+    updates = g.nnz + g.n * p["s"]
+    nbytes = algorithmic_bytes(g.n, g.nnz, p["d"], p["batch"], p["s"], p["precision"])
+    kern_ms = float(np.mean([u for u, _ in upd_ms]))
+    epoch_ms = float(np.mean([t for _, t in upd_ms]))
+    achieved = nbytes / (kern_ms * 1e-3) / 1e9
+    fig = {"value": steps * updates / wall, "ms_per_step": wall * 1e3 / steps, "updates_per_epoch": updates,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(name, p["precision"]),
+                        "kernel": "k_update", "kernel_ms": kern_ms, "epoch_ms": epoch_ms,
+                        "algorithmic_bytes_per_launch": nbytes},
+           "loss_after": loss[0], "health": health}
+    return g, Z0, p, fig
+
+
+def bf16_error_on_ball(g, p, epochs: int = 20, size: int = 10_000) -> dict:
+    """The bf16 form against the FP64 oracle, side by side on the induced
+    subgraph of a BFS ball of `size` vertices (root 0) of the same graph:
+    the largest relative Frobenius error of the master rows over `epochs`
+    epochs from the same start, and the FP32 path's for comparison."""
+    import torch
+    import graphgen as gg
+    import oracle
+    import paper_2009_10035_amd as f2v
+
+    ball, _ = gg.bfs_ball(g, 0, size)
+    Z0 = gg.init_embedding(ball.n, p["d"], p["z_seed"])
+    ref = oracle.run(ball, Z0, oracle.OracleParams.from_dict(dict(p, lr_schedule="const")), epochs)
+    out = {}
+    for prec in ("bf16", "fp32"):
+        rowptr = torch.from_numpy(ball.rowptr).cuda()
+        colidx = torch.from_numpy(ball.colidx).cuda()
+        z = torch.from_numpy(Z0).cuda()
+        tr = f2v.Trainer(rowptr, colidx, z, f2v.make_params(
+            ball.n, ball.nnz, p["d"], batch=p["batch"], s=p["s"], force=p["force"], precision=prec,
+            lr0=p["lr0"], seed=p["seed"]))
+        errs = []
+        for e in range(epochs):
+            tr.epoch(e)
+            tr.sync_embedding()
+            got = z.cpu().numpy().astype(np.float64)
+            errs.append(float(np.linalg.norm(got - ref[e]) / np.linalg.norm(ref[e])))
+        tr.check()
+        tr.close()
+        out[prec] = max(errs)
+    return {"subgraph": f"BFS ball of {ball.n} vertices ({ball.nnz} entries) from vertex 0, {epochs} epochs",
+            "max_rel_err_bf16_vs_fp64": out["bf16"], "max_rel_err_fp32_vs_fp64": out["fp32"]}
 
 
 def main() -> int:
@@ -145,6 +266,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
                     help="override the workload's precision (to compare the two forms on one graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16-form", action="store_true",
+                    help="skip the precision form (sbm4m, bf16) that the default line also carries")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -161,71 +284,27 @@ def main() -> int:
     if args.workload == "serve":
         return serve_bench(args)
     import torch
-    import graphgen as gg
-    import paper_2009_10035_amd as f2v
 
     if not torch.cuda.is_available():
         log("no GPU visible")
         return 1
-    t0 = time.perf_counter()
-    g, p = gg.workload(args.workload)
-    if args.precision:
-        p["precision"] = args.precision
-    log(f"graph {args.workload}: n={g.n} nnz={g.nnz} max degree={int(g.degrees().max())} "
-        f"({time.perf_counter() - t0:.1f}s)")
-    Z0 = gg.init_embedding(g.n, p["d"], p["z_seed"])
-    dev = torch.device("cuda:0")
-    rowptr = torch.from_numpy(g.rowptr).to(dev)
-    colidx = torch.from_numpy(g.colidx).to(dev)
-    z = torch.from_numpy(Z0).to(dev)
-    params = f2v.make_params(g.n, g.nnz, p["d"], batch=p["batch"], s=p["s"], force=p["force"],
-                             precision=p["precision"], lr0=p["lr0"], lr_schedule=p["lr_schedule"],
-                             total_epochs=max(p["total_epochs"], args.warmup + args.steps),
-                             schedule=args.schedule, chunk=args.chunk or None, seed=p["seed"])
-    tr = f2v.Trainer(rowptr, colidx, z, params)
-    for e in range(args.warmup):
-        tr.epoch(e)
-    tr.check()
-    log(f"warm-up done ({args.warmup} epochs)")
-    torch.cuda.synchronize()
-    upd_ms = []
-    t_start = time.perf_counter()
-    for e in range(args.warmup, args.warmup + args.steps):
-        tr.epoch(e)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    tr.check()
-    # per-launch device time of the update kernel, from HIP events on the
-    # library's stream (separate pass so the timed loop has no host syncs)
-    for e in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
-        tr.epoch(e)
-        upd_ms.append(tr.last_epoch_ms())
-    tr.check()
-    loss = tr.loss()
-    log(f"timed {args.steps} epochs in {wall * 1e3:.2f} ms; loss {loss[0]:.6g}")
-    updates = g.nnz + g.n * p["s"]
-    value = args.steps * updates / wall
-    nbytes = algorithmic_bytes(g.n, g.nnz, p["d"], p["batch"], p["s"], p["precision"])
-    kern_ms = float(np.mean([u for u, _ in upd_ms]))
-    epoch_ms = float(np.mean([t for _, t in upd_ms]))
-    achieved = nbytes / (kern_ms * 1e-3) / 1e9
+    g, Z0, p, fig = measure(args.workload, args, args.precision, args.schedule, args.warmup, args.steps)
     if args.copy_calibration:
         nel = args.copy_calibration * (1 << 20) // 4
-        src = torch.empty(nel, dtype=torch.float32, device=dev).uniform_()
+        src = torch.empty(nel, dtype=torch.float32, device="cuda").uniform_()
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB copied 3 times")
-    traffic = recorded_traffic(args.workload, p["precision"])
     out = {
         "metric": "edge+negative updates/sec at 1 MI355X",
-        "value": value,
+        "value": fig["value"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": fig["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -234,17 +313,22 @@ def main() -> int:
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n": g.n, "nnz": g.nnz,
                    "d": p["d"], "batch": p["batch"], "s": p["s"], "force": p["force"],
                    "precision": p["precision"], "schedule": args.schedule,
-                   "updates_per_epoch": updates},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_update", "kernel_ms": kern_ms, "epoch_ms": epoch_ms,
-                     "algorithmic_bytes_per_launch": nbytes},
-        "loss_after": loss[0],
+                   "updates_per_epoch": fig["updates_per_epoch"]},
+        "roofline": fig["roofline"],
+        "loss_after": fig["loss_after"],
+        "health": fig["health"],
     }
-    tr.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(g, Z0, p, args.cpu_seconds)
+    del g, Z0
+    if args.workload == "cl1m" and not args.no_bf16_form:
+        # the precision form on its own workload, measured on the same GPU
+        gb, _, pb, figb = measure("sbm4m", args, None, args.schedule, args.warmup, args.steps)
+        figb.update(config=WORKLOADS["sbm4m"], dtype="bf16")
+        log("bf16 form: error against FP64 on a BFS ball of the same graph")
+        figb["error_vs_fp64"] = bf16_error_on_ball(gb, pb)
+        out["bf16_form"] = figb
     print(json.dumps(out), flush=True)
     return 0
 

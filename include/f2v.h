@@ -66,10 +66,12 @@ typedef enum { F2V_FP32 = 0, F2V_BF16 = 1 } f2v_precision;
 typedef enum { F2V_LR_CONST = 0, F2V_LR_LINEAR = 1 } f2v_lr_schedule;
 typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
 /* Device scheduling of one epoch; all give bit-identical results.
- * DATAFLOW: one persistent launch per epoch (cooperative, sized to the
- *   device's occupancy); batches overlap on the device and a vertex row is read
+ * DATAFLOW: one persistent launch per epoch, sized to the update kernel's
+ *   occupancy limit; batches overlap on the device and a vertex row is read
  *   only once the batch that updates it has published it; work is assigned to
- *   waves statically in batch order.
+ *   waves statically in batch order.  The launch first checks that its whole
+ *   grid is resident at once (which the static order needs); if not, that
+ *   launch hands out work as DYNAMIC does and f2v_check lowers the grid.
  * STRICT: one launch per batch, batches separated by the stream order.
  * DYNAMIC: as DATAFLOW, but running waves claim work in batch order from a
  *   counter, so the launch needs no co-residency and its grid is sized to the
@@ -99,13 +101,20 @@ typedef struct {
                              combined in a fixed order.  0 = default: 64 for
                              n >= 750000, else 32. */
     uint64_t seed;        /* key of every random stream */
+    int32_t late_window;  /* split rows: the neighbours of this many batches
+                             before the row's own are taken last, by the unit
+                             that takes the step (0 .. 2^20); < 0 = default:
+                             28 for n >= 750000, else 24.  Results do not
+                             depend on it. */
+    int32_t fan_in;       /* fan-in of the fixed-order tree that combines a
+                             split row's partial sums, 4 .. 64; 0 = default 8 */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
- * eps = 1e-3, random partition, dataflow schedule, chunk 0 (by size), seed 0.
- * n, nnz and d must still be set. */
+ * eps = 1e-3, random partition, dataflow schedule, chunk 0 (by size), seed 0,
+ * late_window -1 and fan_in 0 (defaults).  n, nnz and d must still be set. */
 void f2v_default_params(f2v_params *p);
 
 /* Host only.  Bytes of device workspace the context needs (a bound from
@@ -140,11 +149,25 @@ f2v_status f2v_loss(f2v_ctx *ctx, double out[3]);
 f2v_status f2v_sync_embedding(f2v_ctx *ctx);
 
 /* Synchronise the stream and report a device-side error raised since the
- * last check (F2V_E_TIMEOUT for an exceeded dependency wait).  After such a
- * wait, later epochs of the context do nothing until this check, so the
- * failed epoch's vertex words are kept: f2v_last_error then gives how many
- * vertices were never published and the earliest of them. */
+ * last check (F2V_E_TIMEOUT for an exceeded dependency wait).  A wait is
+ * bounded by a count of polls (2^22, more than a second of polling), not by a
+ * clock, so a wave that is suspended cannot time out.  After such a wait,
+ * later epochs of the context do nothing until this check, so the failed
+ * epoch's vertex words are kept: f2v_last_error then gives how many vertices
+ * were never published, the earliest of them, and what the first wait to give
+ * up waited for with that word as an atomic read returned it.  If a dataflow
+ * launch since the last check found its grid not co-resident, later epochs
+ * use one block per CU fewer. */
 f2v_status f2v_check(f2v_ctx *ctx);
+
+/* Health record of the context (synchronises the stream): out[0] dataflow
+ * launches that found their grid not co-resident and handed work out by
+ * claiming instead (same results), out[1] polls where an atomic read found a
+ * word set while a later device-scope load of it did not (stale loads; the
+ * waits rely on the atomic read every 64th poll), out[2] the most polls one
+ * dependency wait took, out[3] reserved (0).  *blocks_per_cu (may be NULL):
+ * the dataflow grid's current blocks of 256 threads per CU. */
+f2v_status f2v_health(f2v_ctx *ctx, uint32_t out[4], int32_t *blocks_per_cu);
 
 /* Release the context (no device memory to free; the caller owns it). */
 f2v_status f2v_destroy(f2v_ctx *ctx);

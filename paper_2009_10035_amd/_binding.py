@@ -19,7 +19,7 @@ EXPORTS = (
     "f2v_partition", "f2v_negatives", "f2v_last_epoch_ms", "f2v_set_diagnostics", "f2v_wave_stats",
     "f2v_vertex_trace", "f2v_footprint", "f2v_server_create", "f2v_server_submit",
     "f2v_server_flush", "f2v_server_poll", "f2v_server_query", "f2v_server_drain",
-    "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding",
+    "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding", "f2v_health",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",
@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("lr_schedule", ctypes.c_int32), ("lr0", ctypes.c_float),
         ("eps", ctypes.c_float), ("total_epochs", ctypes.c_int32), ("perm_mode", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("chunk", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("late_window", ctypes.c_int32), ("fan_in", ctypes.c_int32),
     ]
 
 
@@ -112,6 +113,8 @@ def load(build_if_missing: bool = True):
     L.f2v_server_query.restype = st
     L.f2v_random_embedding.argtypes = [P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, P]
     L.f2v_random_embedding.restype = st
+    L.f2v_health.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
+    L.f2v_health.restype = st
     L.f2v_server_last_error.argtypes = [P]
     L.f2v_server_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -127,7 +130,8 @@ def check(status: int, ctx=None) -> None:
 def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force: str = "sigmoid",
                 precision: str = "fp32", lr0: float = 0.02, lr_schedule: str = "const",
                 eps: float = 1e-3, total_epochs: int = 1, perm_mode: str = "random",
-                schedule: str = "dataflow", chunk: int | None = None, seed: int = 0) -> Params:
+                schedule: str = "dataflow", chunk: int | None = None, seed: int = 0,
+                late_window: int | None = None, fan_in: int | None = None) -> Params:
     p = Params()
     load().f2v_default_params(ctypes.byref(p))
     p.n, p.nnz, p.d, p.batch, p.s = n, nnz, d, batch, s
@@ -138,6 +142,10 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
     if chunk:
         p.chunk = chunk
     p.seed = seed
+    if late_window is not None:
+        p.late_window = late_window
+    if fan_in is not None:
+        p.fan_in = fan_in
     return p
 
 

@@ -33,24 +33,30 @@ constexpr int64_t kLargeGraph = 750000;
 constexpr int32_t kLargeLateWindow = 28, kSmallLateWindow = 24;
 constexpr int kMaxChunk = 1 << 20;
 constexpr int kBlock = 256;
-constexpr int kMaxBlocksPerCu = 6;
+constexpr int32_t kDefaultFanIn = 8;
 // Batches of work units one dynamic-schedule grid covers: 4 served 81 jobs/s
 // in closed loop (300 jobs, 16 slots), against 77 at 8, 78 at 2 and 70 at 1.
 constexpr int64_t kDynamicLookahead = 4;
-// Bound on one dependency wait: 250 ms of the device's 100 MHz constant
-// clock.  A unit waits only for the few batches in flight before its own, so
-// a wait cannot outlast its epoch (15 ms for the largest workload measured
-// here); one that reaches the bound means the epoch cannot complete, and the
-// sooner that is reported, the sooner a server can run the job again.
-constexpr uint64_t kSpinTicks = 25000000ull;
+// Bound on one dependency wait, in polls.  A poll is a load plus a sleep of
+// 64 to 1024 cycles, so 2^22 polls are more than a second of waiting, far
+// beyond any legitimate wait (a unit waits only for the few batches in flight
+// before its own; the longest epoch measured here is 15 ms).  A count of polls
+// rather than a clock: a wave that is suspended does not poll, so time spent
+// suspended cannot make a wait give up.
+constexpr uint32_t kMaxPolls = 1u << 22;
+// Static schedule: how long the first waves of a launch wait for the rest of
+// the grid to start before the launch switches to claiming (100 us of the
+// 100 MHz constant clock; dispatching a full grid takes a few us).
+constexpr uint32_t kArriveTicks = 10000u;
 constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
 
 struct Layout {
-  size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, dkey, order, negs, wreal,
-      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, csr_flag, init_rec, scan_scratch,
-      scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket, total;
+  size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, negs, wreal,
+      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, health,
+      csr_flag, init_rec, scan_scratch, scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket,
+      total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
 
@@ -87,8 +93,6 @@ Layout layout_of(const f2v_params& p) {
   L.uoff = take(size_t(n) * 4);
   L.eoff = take(size_t(n) * 4);
   L.loff = take(size_t(n) * 4);
-  L.dkey = take(size_t(n) * 4);
-  L.order = take(size_t(n) * 4);
   L.negs = take(size_t(L.nb) * (p.s > 0 ? p.s : 1) * 4);
   L.wreal = take(size_t(L.nb) * 4);
   L.ereal = take(size_t(L.nb) * 4);
@@ -104,6 +108,7 @@ Layout layout_of(const f2v_params& p) {
   L.hub_cnt = take(size_t(L.hub_slot_cap) * 4);
   L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
   L.err = take(4 * f2v::kErrWords);
+  L.health = take(4 * f2v::kHealthWords);
   L.csr_flag = take(4);
   L.init_rec = take(3 * 8);
   L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
@@ -113,7 +118,7 @@ Layout layout_of(const f2v_params& p) {
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
   L.trace = take(size_t(n) * 8);
-  L.ticket = take(size_t(f2v::kMaxClaimClasses) * f2v::kClaimStride * 4);
+  L.ticket = take(size_t(f2v::kTicketWords) * 4);
   L.total = off;
   return L;
 }
@@ -153,6 +158,9 @@ f2v_status validate(const f2v_params* p, std::string* msg) {
       p->schedule != F2V_SCHED_DYNAMIC)
     return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow, strict or dynamic");
   if (p->chunk < 0 || p->chunk > kMaxChunk) return fail(msg, F2V_E_INVALID_ARG, "chunk must be in [0, 2^20]");
+  if (p->late_window > (1 << 20)) return fail(msg, F2V_E_INVALID_ARG, "late_window must be at most 2^20");
+  if (p->fan_in != 0 && (p->fan_in < 4 || p->fan_in > 64))
+    return fail(msg, F2V_E_INVALID_ARG, "fan_in must be 0 (default) or in [4, 64]");
   const Layout L = layout_of(*p);
   if (L.tmap_cap >= (int64_t{1} << 31)) return fail(msg, F2V_E_INVALID_ARG, "too many work units for int32 tickets");
   return F2V_OK;
@@ -173,23 +181,22 @@ struct f2v_ctx {
   int cur = 0;
   const Variant* var = nullptr;
   const void* update_fn = nullptr;  // var's update kernel for this d
-  int update_grid = 0;
+  int update_grid = 0;      // grid of the static (dataflow) schedule: blocks_per_cu per CU
+  int blocks_per_cu = 0;    // the occupancy limit, less one for every launch found not co-resident
   int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit or the job's size
   int cus = 0;
-  bool cooperative = true;  // launch the dataflow kernel with the co-residency guarantee
+  uint32_t fallbacks_seen = 0;  // health[kHealthFallback] at the last check
   bool diagnostics = false; // collect per-wave counters in dataflow epochs
   int64_t stat_waves = 0;   // waves of the last epoch with counters
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   bool timed = false;
   bool record_events = true;  // off while a server captures the context's work into a graph
-  int32_t fan_in = 8;         // combining-tree fan-in (F2V_FAN_IN)
-  int32_t sort = 0;           // readiness order inside batches (F2V_SORT=1)
+  int32_t fan_in = kDefaultFanIn;          // combining-tree fan-in
   int32_t late_window = kSmallLateWindow;  // batches whose neighbours a split row takes last
-  // Failure drills, forced from the host (F2V_HOLD_VERTEX, F2V_WAIT_BOUND_US):
+  // Failure drills, forced from the host (F2V_HOLD_VERTEX, F2V_WAIT_POLLS):
   // a vertex whose publication is withheld, and the wait bound.
   int32_t hold = -1;
-  uint64_t spin_ticks = kSpinTicks;
-  int32_t claim_classes = 0;  // dataflow: 0 static round robin, else claim classes (F2V_CLAIM_CLASSES)
+  uint32_t max_polls = kMaxPolls;
   int64_t nsplit = 0;         // rows of degree above chunk
   int64_t hub_total = 0;      // combining-tree slots of all split rows
   std::string err;
@@ -220,15 +227,21 @@ float epoch_lr(const f2v_params& p, int32_t e) {
 namespace f2v {
 // Message for a device error record (see kErrWords).
 std::string describe_timeout(const uint32_t* e) {
-  char buf[320];
+  char buf[480];
+  int k;
   if (e[1] != 0)
-    std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
-                  "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
+    k = std::snprintf(buf, sizeof(buf),
+                      "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
+                      "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
   else
-    std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound (after it gave up, every vertex of the epoch "
-                  "was published)");
+    k = std::snprintf(buf, sizeof(buf),
+                      "a device dependency wait exceeded its bound (after the waits stopped, every vertex of the "
+                      "epoch was published)");
+  const uint32_t what = e[kErrWaitedFor];
+  if (what != 0 && k > 0 && k < static_cast<int>(sizeof(buf)))
+    std::snprintf(buf + k, sizeof(buf) - k, "; the first wait to give up waited for %s %u, whose word an atomic "
+                  "read returned as 0x%08x", (what & kErrFlagWait) ? "the early sum of split row" : "vertex",
+                  (what & ~kErrFlagWait) - 1u, e[kErrWaitedWord]);
   return buf;
 }
 }  // namespace f2v
@@ -250,6 +263,8 @@ void f2v_default_params(f2v_params* p) {
   p->schedule = F2V_SCHED_DATAFLOW;
   p->chunk = 0;
   p->seed = 0;
+  p->late_window = -1;
+  p->fan_in = 0;
 }
 
 f2v_status f2v_footprint(const f2v_params* p, size_t* bytes) {
@@ -331,57 +346,44 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   if ((he = hipGetDevice(&dev)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
   if ((he = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
+  // The occupancy limit of the update kernel from its register (VGPR, SGPR)
+  // and LDS use.  It is an upper bound: the static schedule checks at every
+  // launch that the whole grid became resident, switches that launch to
+  // claiming if not, and f2v_check then lowers the grid by one block per CU.
   int per_cu = 0;
   if ((he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->update_fn, kBlock, 0)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("occupancy query: ") + hipGetErrorString(he));
-  if (const char* env = std::getenv("F2V_UPDATE_BLOCKS_PER_CU")) {
-    const int want = std::atoi(env);
-    if (want >= 1 && want < per_cu) per_cu = want;
-  }
-  // The dataflow schedule needs every block resident.  With seven blocks per
-  // CU (a kernel instance of 69 VGPRs, for which the occupancy query reports
-  // seven) the cooperative launch was not fully resident on MI355X and waits
-  // ran into their bound; six and fewer were, so the grid stays at six.
-  if (per_cu > kMaxBlocksPerCu) per_cu = kMaxBlocksPerCu;
   if (per_cu < 1) per_cu = 1;
+  c->blocks_per_cu = per_cu;
   c->update_grid = per_cu * c->cus;
-  // F2V_COOPERATIVE=0 launches the same grid without the cooperative API (some
-  // profilers do not support cooperative launches); the grid is still sized to
-  // the occupancy limit, and a wait that cannot complete ends at its bound.
-  if (const char* env = std::getenv("F2V_COOPERATIVE")) c->cooperative = std::atoi(env) != 0;
-  if (const char* env = std::getenv("F2V_FAN_IN")) {
-    const int x = std::atoi(env);
-    if (x >= 4 && x <= 64) c->fan_in = x;
-  }
-  if (const char* env = std::getenv("F2V_SORT")) c->sort = std::atoi(env) != 0;
-  if (const char* env = std::getenv("F2V_CLAIM_CLASSES")) {
-    const int x = std::atoi(env);
-    if (x >= 0 && x <= f2v::kMaxClaimClasses) c->claim_classes = x;
-  }
-  c->late_window = p->n >= kLargeGraph ? kLargeLateWindow : kSmallLateWindow;
-  if (const char* env = std::getenv("F2V_LATE_WINDOW")) {
-    const int x = std::atoi(env);
-    if (x >= 0 && x <= (1 << 20)) c->late_window = x;
-  }
+  c->fan_in = p->fan_in > 0 ? p->fan_in : kDefaultFanIn;
+  c->late_window = p->late_window >= 0 ? p->late_window : (p->n >= kLargeGraph ? kLargeLateWindow : kSmallLateWindow);
+  // host-forced failure drills (tests of the wait bound and the post-mortem)
   if (const char* env = std::getenv("F2V_HOLD_VERTEX")) {
     const long long x = std::atoll(env);
     if (x >= 0 && x < p->n) c->hold = static_cast<int32_t>(x);
   }
-  if (const char* env = std::getenv("F2V_WAIT_BOUND_US")) {
+  // a static grid larger than the device holds at once (the launch must then
+  // detect it and claim)
+  if (const char* env = std::getenv("F2V_DATAFLOW_BLOCKS_PER_CU")) {
+    const int x = std::atoi(env);
+    if (x >= 1 && x <= 64) {
+      c->blocks_per_cu = x;
+      c->update_grid = x * c->cus;
+    }
+  }
+  if (const char* env = std::getenv("F2V_WAIT_POLLS")) {
     const long long x = std::atoll(env);
-    if (x >= 1000 && x <= 100000000) c->spin_ticks = static_cast<uint64_t>(x) * 100u;  // 100 MHz clock
+    if (x >= 64 && x <= (1ll << 30)) c->max_polls = static_cast<uint32_t>(x);
   }
   {
     // The dynamic schedule (jobs sharing the device) gets one wave per group
     // of about kDynamicLookahead batches, at most the occupancy limit: a
     // batch's units can only run once the batches just before it are done,
     // so more waves would mostly poll while other jobs need the CUs.
-    // F2V_DYNAMIC_LOOKAHEAD overrides the lookahead (0: the occupancy limit).
-    int64_t lookahead = kDynamicLookahead;
-    if (const char* env = std::getenv("F2V_DYNAMIC_LOOKAHEAD")) lookahead = std::atoi(env);
     const int64_t slots = slots_of(c->var);
     const int64_t per_batch = (int64_t(p->batch) * 5 / 4 + slots - 1) / slots;  // units incl. splits
-    const int64_t groups = lookahead > 0 ? lookahead * per_batch : (L.tmap_cap + slots - 1) / slots;
+    const int64_t groups = kDynamicLookahead * per_batch;
     int64_t blocks = (groups + (kBlock / 64) - 1) / (kBlock / 64);
     if (blocks < 1) blocks = 1;
     if (blocks > c->update_grid) blocks = c->update_grid;
@@ -399,6 +401,7 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   const hipStream_t s = c->stream;
   if ((he = f2v::launch_fill_u32(flag, 0u, 1, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(errw, 0u, f2v::kErrWords, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.health), 0u, f2v::kHealthWords, s)) != hipSuccess ||
       (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
       (he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
@@ -444,8 +447,6 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   SetupArgs sa{};
   sa.rowptr = c->rowptr;
   sa.colidx = c->colidx;
-  sa.dkey = c->at<int32_t>(L.dkey);
-  sa.order = c->at<int32_t>(L.order);
   sa.perm = c->at<int32_t>(L.perm);
   sa.word = c->at<uint32_t>(L.word);
   sa.bat = L.nb <= 65536 ? c->at<uint16_t>(L.bat) : nullptr;
@@ -478,7 +479,6 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.seed = p.seed;
   sa.epoch = static_cast<uint32_t>(epoch);
   sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
-  sa.sort = c->sort;
   sa.err = c->at<uint32_t>(L.err);
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
@@ -509,6 +509,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.hub_cnt = c->at<uint32_t>(L.hub_cnt);
   A.hub_part = c->at<float>(L.hub_part);
   A.err = c->at<uint32_t>(L.err);
+  A.health = c->at<uint32_t>(L.health);
   A.n = p.n;
   A.d = p.d;
   A.b = p.batch;
@@ -517,10 +518,11 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.force = p.force;
   A.lr = epoch_lr(p, epoch);
   A.eps = p.eps;
-  A.spin_ticks = c->spin_ticks;
+  A.max_polls = c->max_polls;
+  A.arrive_ticks = kArriveTicks;
   A.hold = c->hold;
   A.ticket = c->at<uint32_t>(L.ticket);
-  A.classes = 0;
+  A.claim = 0;
   A.fan_in = c->fan_in;
   A.late_window = c->late_window;
   A.wave_stats = nullptr;
@@ -532,17 +534,14 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (p.schedule == F2V_SCHED_DYNAMIC) {
     A.strict_batch = -1;
-    A.classes = 1;
+    A.claim = 1;
     void* args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
   } else if (p.schedule == F2V_SCHED_DATAFLOW) {
+    // static round robin; the kernel checks co-residency and claims if needed
     A.strict_batch = -1;
-    A.classes = c->claim_classes;
     void* args[] = {&A};
-    if (c->cooperative)
-      HIP_TRY(c, hipLaunchCooperativeKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
-    else
-      HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
+    HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
   } else {
     const int64_t groups_hint = (p.batch + slots - 1) / slots;
     int grid = static_cast<int>((groups_hint + 3) / 4);
@@ -612,14 +611,35 @@ f2v_status f2v_check(f2v_ctx* c) {
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   uint32_t e[f2v::kErrWords] = {};
+  uint32_t h[f2v::kHealthWords] = {};
   HIP_TRY(c, f2v::launch_postmortem(c->at<uint32_t>(c->L.word), c->p.n, c->at<uint32_t>(c->L.err), c->stream));
+  HIP_TRY(c, hipMemcpyAsync(e, c->at<uint32_t>(c->L.err), sizeof(e), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(h, c->at<uint32_t>(c->L.health), sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  HIP_TRY(c, hipMemcpy(e, c->at<uint32_t>(c->L.err), sizeof(e), hipMemcpyDeviceToHost));
+  // a static launch found its grid not co-resident: later epochs use one
+  // block per CU fewer (results do not depend on the grid)
+  if (h[f2v::kHealthFallback] != c->fallbacks_seen) {
+    c->fallbacks_seen = h[f2v::kHealthFallback];
+    if (c->blocks_per_cu > 1) {
+      --c->blocks_per_cu;
+      c->update_grid = c->blocks_per_cu * c->cus;
+    }
+  }
   if (e[0] != 0) {
     HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, f2v::kErrWords, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return fail(&c->err, F2V_E_TIMEOUT, f2v::describe_timeout(e));
   }
+  return F2V_OK;
+}
+
+f2v_status f2v_health(f2v_ctx* c, uint32_t out[4], int32_t* blocks_per_cu) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(&c->err, F2V_E_INVALID_ARG, "out is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(out, c->at<uint32_t>(c->L.health), sizeof(uint32_t) * f2v::kHealthWords,
+                       hipMemcpyDeviceToHost));
+  if (blocks_per_cu) *blocks_per_cu = c->blocks_per_cu;
   return F2V_OK;
 }
 

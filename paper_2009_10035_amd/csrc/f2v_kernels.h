@@ -15,13 +15,29 @@ constexpr uint32_t kPublished = 0x80000000u;
 // partition kernels return at once), so the vertex words of the epoch that
 // failed are kept, and a post-mortem fills [1] the number of vertices never
 // published in it, [2] the earliest batch among them, [3] one such vertex of
-// that batch and [4] its word.
-constexpr int kErrWords = 5;
+// that batch and [4] its word.  The first wait to give up records [5] what it
+// waited for (vertex + 1, or split row + 1 with bit 31 set for the flag of the
+// row's early sum) and [6] that word as an atomic read-modify-write returned it
+// at the give-up, a read that cannot be served from a stale cache line.
+constexpr int kErrWords = 8;
+constexpr int kErrWaitedFor = 5, kErrWaitedWord = 6;
+constexpr uint32_t kErrFlagWait = 0x80000000u;
 
-// Claim counters of the claiming schedules: at most kMaxClaimClasses, each
-// in its own 128-byte line.
-constexpr int kMaxClaimClasses = 1024;
+// Health counters of a context (never reset by epochs; zeroed at init):
+// [0] launches of the static schedule that found the grid not co-resident and
+// switched to claiming, [1] polls where an atomic read found a row published
+// while a later plain device-scope load of the same word still read it
+// unpublished, [2] the most polls any single wait took.
+constexpr int kHealthWords = 4;
+constexpr int kHealthFallback = 0, kHealthStale = 1, kHealthMaxPolls = 2;
+
+// Claim counter (word 0) and arrival word (word kClaimStride) of an epoch's
+// update launch, each in its own 128-byte line; reset by the prologue.
 constexpr int kClaimStride = 32;
+constexpr int kTicketWords = 2 * kClaimStride;
+// Arrival word: count of waves that have started, bit 31 set once the launch
+// switched to claiming.
+constexpr uint32_t kClaimMode = 0x80000000u;
 
 // Kinds of work unit.  A row of degree at most `chunk` is one WHOLE unit (its
 // neighbours, the batch's negatives, the step).  A longer (split) row has its
@@ -87,6 +103,7 @@ struct EpochArgs {
                             // early sum (all zero at the start of an epoch)
   float* hub_part;          // tree node -> partial sum [d]
   uint32_t* err;            // device error record [kErrWords] (word 0 bit 0: a wait exceeded its bound)
+  uint32_t* health;         // health counters [kHealthWords]
   uint64_t* wave_stats;     // optional [waves][kWaveStats] cycle counters (nullptr: off)
   uint32_t* trace;          // optional [n][2] wall-clock ticks: end of the last wait of the
                             // row's final unit, and its publication (nullptr: off)
@@ -95,9 +112,13 @@ struct EpochArgs {
   float lr, eps;
   int32_t strict_batch;     // >= 0: process only this batch, no waits
   int32_t strict_late;      // with strict_batch: 0 its whole and early units, 1 its late units
-  uint64_t spin_ticks;      // bound on one dependency wait, in ticks of the constant clock
-  uint32_t* ticket;         // claim counters (kClaimStride words apart), or nullptr
-  int32_t classes;          // > 0: waves claim groups from `classes` counters, else static
+  uint32_t max_polls;       // bound on one dependency wait, in polls (a suspended wave
+                            // does not poll, so a suspension cannot trip it)
+  uint32_t arrive_ticks;    // static schedule: how long (constant-clock ticks) the first
+                            // waves wait for the whole grid to start before claiming
+  uint32_t* ticket;         // claim counter, then the arrival word (kClaimStride apart)
+  int32_t claim;            // 1: waves claim groups from the counter; 0: static round
+                            // robin, checked for co-residency at the start
   int32_t fan_in;           // fan-in of the combining tree of split rows
   int32_t late_window;      // batches before a unit's own whose rows are taken last
   int32_t hold;             // >= 0: this vertex's row is written but never published (a
@@ -119,8 +140,6 @@ struct SetupArgs {
   int32_t* uoff;            // position -> offset of its whole unit among its batch's whole units
   int32_t* eoff;            // position -> offset of its early units among its batch's early units
   int32_t* loff;            // position -> offset of its late unit among its batch's late units
-  int32_t* dkey;            // position -> latest earlier batch its row depends on (-1: none)
-  int32_t* order;           // positions of each batch, sorted by dkey (then position)
   int32_t* negs;
   int32_t* wreal;           // [nb] whole units of each batch
   int32_t* ereal;           // [nb] early units of each batch
@@ -132,7 +151,7 @@ struct SetupArgs {
   int32_t* lstart;          // [nb] first ticket of each batch's second part
   Unit* units;
   int32_t* ngroups;
-  uint32_t* ticket;         // claim counters (reset here)
+  uint32_t* ticket;         // claim counter and arrival word (reset here)
   int64_t n, nsplit;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave
   int32_t late_window;      // batches before a split row's own whose neighbours go late
@@ -141,7 +160,6 @@ struct SetupArgs {
   int32_t identity;
   int32_t feistel_half;
   uint32_t feistel_mask;
-  int32_t sort;             // order each batch's rows by readiness
   const uint32_t* err;      // the context's error record: set = do nothing
 };
 

@@ -242,34 +242,6 @@ __global__ void k_sort_late(SetupArgs A) {
   }
 }
 
-// K1b: 16 lanes per position: the latest earlier batch among the row's
-// neighbours (the batch whose publication it will wait for last).
-__global__ void k_readiness(SetupArgs A, const int32_t* colidx) {
-  if (*A.err != 0u) return;  // an earlier epoch failed
-  const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t p = tid >> 4;
-  const int l = static_cast<int>(tid & 15);
-  int32_t best = -1;
-  if (p < A.n) {
-    const int32_t u = A.perm[p];
-    const int32_t k = static_cast<int32_t>(p / A.b);
-    const int64_t r1 = A.rowptr[u + 1];
-    for (int64_t e = A.rowptr[u] + l; e < r1; e += 16) {
-      const int32_t kb = static_cast<int32_t>(A.word[colidx[e]]);
-      if (kb < k && kb > best) best = kb;
-    }
-  }
-#pragma unroll
-  for (int m = 1; m < 16; m <<= 1) {
-    const int32_t o = __shfl_xor(best, m, 64);
-    best = o > best ? o : best;
-  }
-  if (p < A.n && l == 0) A.dkey[p] = best;
-}
-
-// Batches larger than this keep position order (no readiness sort).
-constexpr int kSortMax = 2048;
-
 // Work units of the row at a position: whole units in the low 32 bits, late
 // units in the high 32 bits (one of the two is 1, the other 0).
 __device__ __forceinline__ int64_t whole_late(const SetupArgs& A, int32_t u) {
@@ -284,18 +256,17 @@ __device__ __forceinline__ int64_t early_units(const SetupArgs& A, int32_t u) {
   return (static_cast<int64_t>(A.ecnt[u]) + A.chunk - 1) / A.chunk;
 }
 
-// Block-wide exclusive scan of c over the positions lo..hi (in `order`),
-// writing the offsets through `put` and returning the total.
+// Block-wide exclusive scan of c over the positions lo..hi, writing the
+// offsets through `put` and returning the total.
 template <typename Count, typename Put>
 __device__ int64_t scan_positions(const SetupArgs& A, int64_t lo, int64_t hi, int64_t* lds,
                                   int64_t* tile_total, Count count, Put put) {
   int64_t carry = 0;
   for (int64_t base = lo; base < hi; base += blockDim.x) {
     const int64_t r = base + threadIdx.x;
-    const int32_t p = r < hi ? A.order[r] : 0;
-    const int64_t c = r < hi ? count(A.perm[p]) : 0;
+    const int64_t c = r < hi ? count(A.perm[r]) : 0;
     const int64_t inc = block_inclusive_scan(c, lds);
-    if (r < hi) put(p, carry + inc - c);
+    if (r < hi) put(r, carry + inc - c);
     // the tile total is the last thread's inclusive value
     if (threadIdx.x == blockDim.x - 1) *tile_total = inc;
     __syncthreads();
@@ -305,47 +276,26 @@ __device__ int64_t scan_positions(const SetupArgs& A, int64_t lo, int64_t hi, in
   return carry;
 }
 
-// K2: one block per batch: order the batch's positions by readiness (rows
-// whose dependencies are older first; ties by position), then in that order
-// the offsets of each row's whole, early and late units among the batch's
-// units of that kind, and the batch's counts of each kind.  Rows of one batch
-// are independent, so the order inside a batch changes no result.
+// K2: one block per batch: in position order, the offsets of each row's
+// whole, early and late units among the batch's units of that kind, and the
+// batch's counts of each kind.
 __global__ void k_batch_units(SetupArgs A) {
   if (*A.err != 0u) return;  // an earlier epoch failed
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
-  __shared__ int32_t keys[kSortMax];
   const int32_t k = blockIdx.x;
   const int64_t lo = static_cast<int64_t>(k) * A.b;
   const int64_t hi = lo + A.b < A.n ? lo + A.b : A.n;
-  const int32_t len = static_cast<int32_t>(hi - lo);
-  if (A.sort && len <= kSortMax) {
-    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) keys[i] = A.dkey[lo + i];
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-      const int32_t ki = keys[i];
-      int32_t rank = 0;
-      for (int32_t j = 0; j < len; ++j) {
-        const int32_t kj = keys[j];
-        rank += (kj < ki) || (kj == ki && j < i);
-      }
-      A.order[lo + rank] = static_cast<int32_t>(lo + i);
-    }
-  } else {
-    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) A.order[lo + i] = static_cast<int32_t>(lo + i);
-  }
-  __syncthreads();
-  __threadfence_block();
   // whole and late counts in one scan: the halves never carry into each other
   const int64_t wl = scan_positions(
       A, lo, hi, lds, &tile_total, [&](int32_t u) { return whole_late(A, u); },
-      [&](int32_t p, int64_t ex) {
+      [&](int64_t p, int64_t ex) {
         A.uoff[p] = static_cast<int32_t>(ex & 0xffffffffll);
         A.loff[p] = static_cast<int32_t>(ex >> 32);
       });
   const int64_t ne = scan_positions(
       A, lo, hi, lds, &tile_total, [&](int32_t u) { return early_units(A, u); },
-      [&](int32_t p, int64_t ex) { A.eoff[p] = static_cast<int32_t>(ex); });
+      [&](int64_t p, int64_t ex) { A.eoff[p] = static_cast<int32_t>(ex); });
   if (threadIdx.x == 0) {
     A.wreal[k] = static_cast<int32_t>(wl & 0xffffffffll);
     A.lreal[k] = static_cast<int32_t>(wl >> 32);
@@ -410,7 +360,8 @@ __global__ void k_batch_starts(SetupArgs A) {
     A.bstart[A.nb] = static_cast<int32_t>(carry);
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
   }
-  for (int i = threadIdx.x; i < kMaxClaimClasses; i += blockDim.x) st_coherent_u32(A.ticket + i * kClaimStride, 0u);
+  // the claim counter and the arrival word of the update launch
+  for (int i = threadIdx.x; i < kTicketWords; i += blockDim.x) st_coherent_u32(A.ticket + i, 0u);
   __syncthreads();
   __threadfence_block();
   for (int64_t k = threadIdx.x; k < A.nb; k += blockDim.x) {
@@ -700,7 +651,6 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * (64 / kSortRowsPerWave), 256)), dim3(256), 0, st,
                        a);
   }
-  if (a.sort) hipLaunchKernelGGL(k_readiness, dim3((a.n * 16 + 255) / 256), dim3(256), 0, st, a, a.colidx);
   hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
   hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);
   hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + 2 * static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0,

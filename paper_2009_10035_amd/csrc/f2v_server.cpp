@@ -36,7 +36,7 @@ namespace {
 
 // Words per slot of the completion records: the sequence number, then the
 // job's device error record.
-constexpr size_t kRecWords = 8;
+constexpr size_t kRecWords = 16;
 static_assert(1 + f2v::kErrWords <= kRecWords, "completion record too small");
 
 struct Job {

@@ -60,11 +60,59 @@ struct WaveCounters {
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
+// Atomic read of a word (a read-modify-write): performed where the word
+// lives, so it cannot return a stale cached copy.  The waits below poll with
+// device-scope loads and, on every 64th round, with an atomic read made by the
+// first lane of each group (every lane of a group waits for the same words).
+// When the atomic read finds the bit set and a plain device-scope load issued
+// after it still does not, the stale load is counted in the health record.
+// (A compare-and-swap whose expected value no vertex word or flag ever holds:
+// it fails and returns the current value.  An idempotent or-with-0 would do
+// the same, but the compiler folds that into a plain load.)
+constexpr uint32_t kNeverAWord = 0x7fffffffu;  // batch index 2^31 - 1 > any batch, bit 31 clear
+__device__ __forceinline__ uint32_t atomic_read_u32(const uint32_t* p) {
+  uint32_t expected = kNeverAWord;
+  __hip_atomic_compare_exchange_strong(const_cast<uint32_t*>(p), &expected, kNeverAWord, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return expected;
+}
+
+// Bit `bit` of *p (p may be null: the lane polls nothing) by the group's
+// atomic read; every lane of a group gets the leader's answer.  All 64 lanes
+// must be active.
+template <int G>
+__device__ __forceinline__ bool atomic_poll(const EpochArgs& A, const uint32_t* p, uint32_t bit) {
+  const int lane = threadIdx.x & 63;
+  const bool leader = (lane % G) == 0;
+  uint32_t r = 0;
+  if (leader && p) r = atomic_read_u32(p);
+  if constexpr (G > 1) r = __shfl(r, lane - lane % G, 64);
+  const bool set = (r & bit) != 0u;
+  if (leader && p && set && (ld_coherent_u32(p) & bit) == 0u) atomicAdd(A.health + kHealthStale, 1u);
+  return set;
+}
+
+// A wait that reached its bound: record the first give-up (what it waited for
+// and that word as an atomic read returns it) and raise the error word, which
+// makes every other waiter stop within 64 polls.
+__device__ __forceinline__ void give_up(const EpochArgs& A, uint32_t what, const uint32_t* p) {
+  const uint32_t r = atomic_read_u32(p);
+  if (atomicCAS(A.err + kErrWaitedFor, 0u, what) == 0u) st_coherent_u32(A.err + kErrWaitedWord, r);
+  atomicOr(A.err, 1u);
+}
+
+// Sleep between polls: back off from 64 to 1024 cycles.
+__device__ __forceinline__ void poll_backoff(uint32_t polls) {
+  if (polls < 8) __builtin_amdgcn_s_sleep(1);
+  else if (polls < 32) __builtin_amdgcn_s_sleep(4);
+  else __builtin_amdgcn_s_sleep(16);
+}
+
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
-// Bounded: after spin_ticks of the device's constant clock (or once another
-// wave has reported a timeout) it sets the error word and returns.  Polls
-// back off from 64 to 1024 cycles of sleep.
-template <int U>
+// Bounded by a count of polls (A.max_polls, so a suspended wave cannot trip
+// it), or until another wave has reported a timeout; then it records the
+// give-up and returns.  All 64 lanes must be active.
+template <int G, int U>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
   bool any = false;
@@ -72,35 +120,54 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
   for (int q = 0; q < U; ++q) any |= pend[q];
   if (!__any(any)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
-  const uint64_t t_begin = wall_clock64();
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
-    // each lane polls only its first pending entry: one load per lane and
-    // round keeps the poll traffic small while many waves wait
     any = false;
-    bool polled = false;
+    if ((polls & 63u) != 63u) {
+      // each lane polls its first pending entry, and the next one only if
+      // that one is published: few loads per round while many waves wait
+      bool polled = false;
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      if (pend[q] && !polled) {
-        pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
-        polled = pend[q];
+      for (int q = 0; q < U; ++q) {
+        if (pend[q] && !polled) {
+          pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+          polled = pend[q];
+        }
+        any |= pend[q];
       }
-      any |= pend[q];
+    } else {
+      int32_t v = -1;
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (pend[q] && v < 0) v = vid[q];
+      const bool set = atomic_poll<G>(A, v >= 0 ? A.word + v : nullptr, kPublished);
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (pend[q] && !done) {
+          done = true;
+          pend[q] = !set;
+        }
+        any |= pend[q];
+      }
     }
     if (!__any(any)) break;
     ++polls;
     if ((polls & 63u) == 0) {
-      if (wall_clock64() - t_begin > A.spin_ticks) {
-        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+      if (polls >= A.max_polls) {
+        int32_t v = -1;
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if (pend[q] && v < 0) v = vid[q];
+        if (v >= 0) give_up(A, static_cast<uint32_t>(v) + 1u, A.word + v);
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
     }
-    if (polls < 8) __builtin_amdgcn_s_sleep(1);
-    else if (polls < 32) __builtin_amdgcn_s_sleep(4);
-    else __builtin_amdgcn_s_sleep(16);
+    poll_backoff(polls);
   }
+  if (polls >= 64 && (threadIdx.x & 63) == 0) atomicMax(A.health + kHealthMaxPolls, polls);
   compiler_fence();
   // the unit waited on the chain of publications: finish it ahead of waves
   // doing work that nothing waits for yet
@@ -238,7 +305,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait) wait_published<U>(A, vid, pend, wc);
+  if (kNext && wait) wait_published<G, U>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -430,30 +497,35 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
   }
 }
 
-// Wait until the flag word at `flag` (per lane group; nullptr: none) is set.
-// Bounded like wait_published.
-__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
+// Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
+// the early sum of split row `u`.  Bounded like wait_published.  All 64 lanes
+// must be active.
+template <int G>
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
-  const uint64_t t_begin = wall_clock64();
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
-    if (pend) pend = ld_coherent_u32(flag) == 0u;
+    if ((polls & 63u) != 63u) {
+      if (pend) pend = ld_coherent_u32(flag) == 0u;
+    } else {
+      const bool set = atomic_poll<G>(A, pend ? flag : nullptr, ~0u);
+      if (pend) pend = !set;
+    }
     if (!__any(pend)) break;
     ++polls;
     if ((polls & 63u) == 0) {
-      if (wall_clock64() - t_begin > A.spin_ticks) {
-        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+      if (polls >= A.max_polls) {
+        if (pend) give_up(A, (static_cast<uint32_t>(u) + 1u) | kErrFlagWait, flag);
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
     }
-    if (polls < 8) __builtin_amdgcn_s_sleep(1);
-    else if (polls < 32) __builtin_amdgcn_s_sleep(4);
-    else __builtin_amdgcn_s_sleep(16);
+    poll_backoff(polls);
   }
+  if (polls >= 64 && (threadIdx.x & 63) == 0) atomicMax(A.health + kHealthMaxPolls, polls);
   compiler_fence();
   if (A.wave_stats) {
     wc.wait += clock64() - t0;
@@ -518,7 +590,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, wc);
+    wait_flag<G>(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
@@ -657,6 +729,35 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   }
 }
 
+// Start of a static-schedule launch (lane 0 of each wave): count this wave in
+// the arrival word and wait until the whole grid has started; returns 0 then.
+// If that takes longer than A.arrive_ticks, the grid is not co-resident (or
+// not yet): the first wave to notice marks the launch as claiming, with a
+// compare-and-swap that fails once the last wave has arrived, so every wave
+// takes the same decision; returns 1.  No wave has processed a group before
+// the decision, so either way every unit is run exactly once.
+__device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint32_t nwaves) {
+  uint32_t* arrive = A.ticket + kClaimStride;
+  uint32_t x = atomicAdd(arrive, 1u) + 1u;
+  const uint64_t t0 = wall_clock64();
+#pragma clang loop unroll(disable)
+  while (true) {
+    if (x & kClaimMode) return 1u;
+    if (x == nwaves) return 0u;
+    if (wall_clock64() - t0 > A.arrive_ticks) {
+      const uint32_t seen = atomicCAS(arrive, x, x | kClaimMode);
+      if (seen == x) {
+        atomicAdd(A.health + kHealthFallback, 1u);
+        return 1u;
+      }
+      x = seen;
+      continue;
+    }
+    __builtin_amdgcn_s_sleep(2);
+    x = ld_coherent_u32(arrive);
+  }
+}
+
 template <int G, int V, int R, bool BF16, bool FULL>
 // Packed bf16 rows with one row per wave: sixteen rows in flight need more
 // registers than six waves per SIMD leave; the compiler is held to that
@@ -689,19 +790,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
   WaveCounters& wc = wc_lds[threadIdx.x >> 6];
   if (A.wave_stats || A.trace) wc = WaveCounters{0, 0, 0, 0, 0, 0, 0, 0};
   const uint64_t t_start = A.wave_stats ? clock64() : 0;
+  // The static schedule needs every wave of the grid resident at once; the
+  // launch checks that instead of assuming it (the occupancy limit is an upper
+  // bound that the dispatcher need not reach).
+  bool claim = A.claim != 0;
+  if (!claim && A.strict_batch < 0) {
+    uint32_t c = 0;
+    if (lane == 0) c = join_static_launch(A, static_cast<uint32_t>(nwaves));
+    claim = __builtin_amdgcn_readfirstlane(static_cast<int>(c)) != 0;
+  }
   // Groups a wave processes, in increasing order: static, g = gbeg + wave +
-  // i * nwaves; or claiming, the groups c, c + C, c + 2C, ... of its class
-  // c = wave % C in the order its class's counter hands them out.  One group
-  // ahead is known (its unit record loads while the current one is processed).
-  const int cls = A.classes > 0 ? wave % A.classes : 0;
-  uint32_t* ctr = A.ticket + static_cast<int64_t>(cls) * kClaimStride;
+  // i * nwaves; or claiming, in the order the counter hands them out.  One
+  // group ahead is known (its unit record loads while the current one is
+  // processed), and the claim after it is made before the current group
+  // starts.
   auto following = [&](int g) {
     int64_t t;
-    if (A.classes > 0) {
+    if (claim) {
       uint32_t x = 0;
-      if (lane == 0) x = atomicAdd(ctr, 1u);
-      x = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
-      t = cls + static_cast<int64_t>(A.classes) * x;
+      if (lane == 0) x = atomicAdd(A.ticket, 1u);
+      t = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
     } else {
       t = static_cast<int64_t>(g) + nwaves;
     }

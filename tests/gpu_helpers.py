@@ -23,7 +23,7 @@ def lib_params(g, p: dict, **over):
         precision=q.get("precision", "fp32"), lr0=q["lr0"], lr_schedule=q.get("lr_schedule", "const"),
         eps=q.get("eps", 1e-3), total_epochs=q.get("total_epochs", 1),
         perm_mode=q.get("perm_mode", "random"), schedule=q.get("schedule", "dataflow"),
-        chunk=q.get("chunk", 0), seed=q["seed"])
+        chunk=q.get("chunk", 0), seed=q["seed"], late_window=q.get("late_window"), fan_in=q.get("fan_in"))
 
 
 def oracle_params(p: dict, **over) -> oracle.OracleParams:
@@ -58,3 +58,24 @@ def rel_fro(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def row_rel(a, b) -> float:
+    """Largest per-row relative error max_u |a_u - b_u| / |b_u| (Euclidean
+    norms), with row norms floored at 1% of the RMS row norm so that a row
+    near the origin does not divide by ~0.  A dropped or doubled term in one
+    row shows here even when it is invisible in the Frobenius norm of a
+    million-row matrix."""
+    a = np.asarray(a, dtype=np.float64).reshape(len(a), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    nb = np.linalg.norm(b, axis=1)
+    floor = 1e-2 * np.sqrt(np.mean(nb ** 2)) if nb.size else 1.0
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.maximum(nb, max(floor, 1e-30)))) if nb.size else 0.0
+
+
+def assert_parity(got, ref, fro_tol: float, row_tol: float, what=""):
+    """Relative Frobenius error <= fro_tol and per-row relative error <= row_tol."""
+    f, r = rel_fro(got, ref), row_rel(got, ref)
+    assert f <= fro_tol and r <= row_tol, f"{what}: relative Frobenius {f:.3e} (bound {fro_tol:g}), " \
+                                          f"row-wise max {r:.3e} (bound {row_tol:g})"
+    return f, r

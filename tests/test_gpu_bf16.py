@@ -31,10 +31,13 @@ def bf16_bits(x):
     return t.view(torch.int16).numpy().astype(np.int32)
 
 
-@pytest.mark.parametrize("force,d", [("student_t", 64), ("sigmoid", 128), ("student_t", 2), ("sigmoid", 30)])
-def test_bf16_matches_emulation_one_epoch(force, d):
+# ("student_t", 128, 10) is the precision workload's configuration: one row
+# per wave with sixteen packed bf16 rows in flight
+@pytest.mark.parametrize("force,d,s", [("student_t", 64, 5), ("sigmoid", 128, 5), ("student_t", 2, 5),
+                                       ("sigmoid", 30, 5), ("student_t", 128, 10)])
+def test_bf16_matches_emulation_one_epoch(force, d, s):
     g = gg.erdos_renyi(3000, 12.0, 4)
-    p = dict(d=d, batch=100, s=5, force=force, lr0=0.02, seed=21, precision="bf16")
+    p = dict(d=d, batch=100, s=s, force=force, lr0=0.02, seed=21, precision="bf16")
     Z0 = gg.init_embedding(g.n, d, 3)
     got = gpu_run(g, Z0, p, 1)[0]
     ref = oracle.epoch(g, Z0, 0, oracle_params(p), emul=True)

@@ -1,7 +1,7 @@
 """Failure detection on the device, forced from the host (no kernel faults
 or hangs: every wait is bounded).  A vertex whose publication is withheld
 (F2V_HOLD_VERTEX) makes the rows that depend on it wait until the wait bound
-(F2V_WAIT_BOUND_US, short here): the epoch reports F2V_E_TIMEOUT with a
+(F2V_WAIT_POLLS, a short count of polls here): the epoch reports F2V_E_TIMEOUT with a
 post-mortem naming the vertex, later epochs do nothing until the check, and
 the server reports the job after running it once more."""
 import numpy as np
@@ -38,7 +38,7 @@ def held_case():
 def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
     g, p, v = held_case()
     monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
-    monkeypatch.setenv("F2V_WAIT_BOUND_US", "20000")
+    monkeypatch.setenv("F2V_WAIT_POLLS", "4096")
     rowptr, colidx = device_graph(g)
     z = torch.from_numpy(np.ascontiguousarray(gg.init_embedding(g.n, p["d"], 3), dtype=np.float32)).cuda()
     tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p, total_epochs=3, schedule=schedule))
@@ -49,6 +49,9 @@ def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
     assert ei.value.name == "F2V_E_TIMEOUT"
     msg = str(ei.value)
     assert "1 vertices were never published" in msg and f"vertex {v} of batch 0" in msg, msg
+    # the first wait to give up waited for that vertex, and an atomic read of
+    # its word (batch 0, never published) confirms it was not published
+    assert f"waited for vertex {v}, whose word an atomic read returned as 0x00000000" in msg, msg
     tr.check()    # the error was reported once
     tr.close()
 
@@ -56,7 +59,7 @@ def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
 def test_server_runs_a_stalled_job_again_and_reports_it(monkeypatch):
     g, p, v = held_case()
     monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
-    monkeypatch.setenv("F2V_WAIT_BOUND_US", "20000")
+    monkeypatch.setenv("F2V_WAIT_POLLS", "4096")
     job = JobSpec(request=0, arrival=0.0, graph=g, d=p["d"], precision="fp32", force="sigmoid", epochs=2,
                   seed=p["seed"], batch=p["batch"], s=p["s"], lr0=p["lr0"])
     srv = DeviceServer(hbm_budget=1 << 30, max_slots=2)
@@ -66,3 +69,31 @@ def test_server_runs_a_stalled_job_again_and_reports_it(monkeypatch):
     assert out["failed"] == 1 and out["retried"] == 1 and rec["status"] == "F2V_E_TIMEOUT"
     for m in rec["retried"] + [rec["error"]]:
         assert f"vertex {v} of batch 0" in m, m
+
+
+def test_oversubscribed_static_grid_claims_and_matches(monkeypatch):
+    """The dataflow launch with far more blocks than the device holds at once
+    (F2V_DATAFLOW_BLOCKS_PER_CU, a host-forced drill): the waves that start
+    find the grid not co-resident, switch the launch to claiming, and the
+    epoch gives the same bits as the strict schedule.  f2v_check then lowers
+    the grid, and the health record counts the switch."""
+    from gpu_helpers import gpu_run
+    g = gg.chung_lu(20000, 2.1, 20.0, 3)
+    p = dict(d=128, batch=128, s=5, force="sigmoid", lr0=0.02, seed=5)
+    Z0 = gg.init_embedding(g.n, p["d"], 3)
+    ref = gpu_run(g, Z0, p, 2, schedule="strict")
+    monkeypatch.setenv("F2V_DATAFLOW_BLOCKS_PER_CU", "40")
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(Z0, dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p))
+    assert tr.health()["blocks_per_cu"] == 40
+    tr.epoch(0)
+    tr.check()
+    h = tr.health()
+    assert h["fallbacks"] == 1 and h["blocks_per_cu"] == 39 and h["stale_loads"] == 0, h
+    tr.epoch(1)
+    tr.sync_embedding()
+    tr.check()
+    got = z.cpu().numpy()
+    tr.close()
+    assert np.array_equal(got, ref[-1])

@@ -12,11 +12,17 @@ import torch
 import graphgen as gg
 import oracle
 import paper_2009_10035_amd as f2v
-from gpu_helpers import device_graph, gpu_run, lib_params, oracle_params, rel_fro
+from gpu_helpers import assert_parity, device_graph, gpu_run, lib_params, oracle_params, rel_fro, row_rel
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+# Row-wise bounds: one epoch from the same FP32 state, every row within 1e-5
+# of its norm (FP32 rounding of a row's sum is ~1e-7 of it); free-running
+# trajectories, where rounding is amplified from epoch to epoch, 1e-3 (a value
+# above that flags a localised bug rather than drift).
+ROW_TOL_ONE_EPOCH = 1e-5
+ROW_TOL_FREE = 1e-3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -49,6 +55,7 @@ def test_er1k_free_running_20_epochs(schedule):
     errs = [rel_fro(a, b) for a, b in zip(got, ref)]
     print("per-epoch relative error", ["%.2e" % e for e in errs])
     assert max(errs) <= TOL
+    assert max(row_rel(a, b) for a, b in zip(got, ref)) <= ROW_TOL_FREE
 
 
 def test_er1k_one_epoch_from_shared_state():
@@ -59,9 +66,7 @@ def test_er1k_one_epoch_from_shared_state():
         start = (Z0 if e == 0 else states[e - 1]).astype(np.float32)
         ref = oracle.epoch(g, start, e, oracle_params(p))
         got = gpu_run(g, start, p, 1, first=e)[0]
-        err = rel_fro(got, ref)
-        rowmax = np.max(np.abs(got - ref) / (np.abs(ref).max(axis=1, keepdims=True) + 1e-30))
-        assert err <= TOL and rowmax < 1e-3, (e, err, rowmax)
+        assert_parity(got, ref, TOL, ROW_TOL_ONE_EPOCH, f"epoch {e}")
 
 
 @pytest.mark.parametrize("maker,chunk", [
@@ -82,20 +87,19 @@ def test_dataflow_equals_strict_and_oracle(maker, chunk, d, force):
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, y) and np.array_equal(x, z)
     ref = oracle.epoch(g, Z0, 0, oracle_params(p))
-    assert rel_fro(a[0], ref) <= TOL
+    assert_parity(a[0], ref, TOL, ROW_TOL_ONE_EPOCH)
 
 
 @pytest.mark.parametrize("window", [0, 1, 8, 1 << 20])
 @pytest.mark.parametrize("fan_in", [4, 8])
-def test_split_rows_late_window(window, fan_in, monkeypatch):
+def test_split_rows_late_window(window, fan_in):
     """Split rows under every early/late division: no late neighbours (window
     0), a few, and all neighbours of earlier batches late (so some rows have
     no early units and others one or many, with trees of several levels).
     The three schedules agree bit for bit, the oracle within the tolerance."""
-    monkeypatch.setenv("F2V_LATE_WINDOW", str(window))
-    monkeypatch.setenv("F2V_FAN_IN", str(fan_in))
     g = gg.chung_lu(20000, 2.1, 20.0, 3)
-    p = dict(d=32, batch=96, s=5, force="sigmoid", lr0=0.02, seed=5, chunk=8)
+    p = dict(d=32, batch=96, s=5, force="sigmoid", lr0=0.02, seed=5, chunk=8, late_window=window,
+             fan_in=fan_in)
     Z0 = gg.init_embedding(g.n, p["d"], 3)
     a = gpu_run(g, Z0, p, 2, schedule="dataflow")
     b = gpu_run(g, Z0, p, 2, schedule="strict")
@@ -103,7 +107,7 @@ def test_split_rows_late_window(window, fan_in, monkeypatch):
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, y) and np.array_equal(x, z)
     ref = oracle.epoch(g, Z0, 0, oracle_params(p))
-    assert rel_fro(a[0], ref) <= TOL
+    assert_parity(a[0], ref, TOL, ROW_TOL_ONE_EPOCH)
 
 
 def test_run_twice_and_resume_bitwise():
@@ -135,6 +139,7 @@ def test_dimensions(d, force):
     pert = oracle.run(g, Zp, oracle_params(p), 2)
     for x, y, z in zip(got, ref, pert):
         assert rel_fro(x, y) <= max(TOL, 10 * rel_fro(z, y))
+        assert row_rel(x, y) <= max(ROW_TOL_FREE, 10 * row_rel(z, y))
 
 
 @pytest.mark.parametrize("case", ["n1", "isolated", "s0", "b1", "b_ge_n", "identity", "selfloop_dup",
@@ -172,7 +177,9 @@ def test_edge_cases(case):
     got = gpu_run(g, Z0, p, 3)
     ref = oracle.run(g, Z0, oracle_params(p), 3)
     for x, y in zip(got, ref):
-        assert rel_fro(x, y) <= TOL, case
+        assert_parity(x, y, TOL, ROW_TOL_FREE, case)
+    one = oracle.epoch(g, Z0, 0, oracle_params(p))
+    assert_parity(got[0], one, TOL, ROW_TOL_ONE_EPOCH, case)
     got_s = gpu_run(g, Z0, p, 3, schedule="strict")
     got_d = gpu_run(g, Z0, p, 3, schedule="dynamic")
     for x, y, z in zip(got, got_s, got_d):

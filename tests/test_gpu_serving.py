@@ -8,9 +8,10 @@ import pytest
 import torch
 
 import graphgen as gg
+import oracle
 import paper_2009_10035_amd as f2v
 from paper_2009_10035_amd.serve import DeviceServer, JobSpec, run_requests
-from gpu_helpers import gpu_run
+from gpu_helpers import gpu_run, oracle_params, rel_fro, row_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +41,7 @@ def test_each_result_same_alone_and_in_the_mix():
     mix = run_requests(jobs, srv, keep=[j.request for j in jobs])
     srv.close()
     assert mix["jobs"] == len(jobs) and mix["failed"] == 0, [r["error"] for r in mix["records"].values() if r["error"]]
+    assert mix["retried"] == 0, [r["retried"] for r in mix["records"].values() if r["retried"]]
     for j in jobs[:8]:
         alone_srv = DeviceServer(hbm_budget=8 << 30, max_slots=1)
         alone = run_requests([JobSpec(**{**j.__dict__, "arrival": 0.0})], alone_srv, keep=[j.request])
@@ -50,6 +52,33 @@ def test_each_result_same_alone_and_in_the_mix():
         p = dict(d=j.d, batch=j.batch, s=j.s, force=j.force, lr0=j.lr0, seed=j.seed, precision=j.precision)
         ref = gpu_run(j.graph, z0, p, j.epochs, snapshots=False, schedule="dynamic")[-1]
         assert np.array_equal(ref, mix["results"][j.request]), j.request
+
+
+def test_mix_results_match_the_oracle():
+    """Every job of a served mix against the FP64 oracle run on the same
+    start: FP32 jobs within 1e-5 (or 10x the oracle's own response to a
+    one-ulp perturbation of the start, for trajectories that amplify
+    rounding), bf16 jobs within the bf16 form's stated bound (1e-3)."""
+    jobs = mix_jobs()
+    for j in jobs:
+        j.epochs = 2
+    srv = DeviceServer(hbm_budget=8 << 30, max_slots=6)
+    mix = run_requests(jobs, srv, keep=[j.request for j in jobs])
+    srv.close()
+    assert mix["failed"] == 0 and mix["retried"] == 0
+    rng = np.random.default_rng(0)
+    for j in jobs:
+        z0 = f2v.random_embedding(j.graph.n, j.d, 12345 + j.request).cpu().numpy()
+        p = dict(d=j.d, batch=j.batch, s=j.s, force=j.force, lr0=j.lr0, seed=j.seed)
+        ref = oracle.run(j.graph, z0, oracle_params(p), j.epochs)[-1]
+        got = mix["results"][j.request]
+        if j.precision == "bf16":
+            assert rel_fro(got, ref) <= 1e-3, j.request
+            continue
+        zp = z0.astype(np.float64) * (1 + 2.0**-24 * rng.choice([-1.0, 1.0], size=z0.shape))
+        pert = oracle.run(j.graph, zp, oracle_params(p), j.epochs)[-1]
+        assert rel_fro(got, ref) <= max(1e-5, 10 * rel_fro(pert, ref)), (j.request, rel_fro(got, ref))
+        assert row_rel(got, ref) <= max(1e-3, 10 * row_rel(pert, ref)), j.request
 
 
 def test_random_embedding_uniform():
