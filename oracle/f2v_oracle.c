@@ -18,7 +18,15 @@
  *     at the start of the batch (Algorithm 2), then the step of Eq. 10 applied
  *     to the batch vertices only;
  *   - the negative-sampled loss of Eq. 2 (Eqs. 3 and 7), with a fixed set of
- *     evaluation negatives per vertex so that it is a function of Z alone.
+ *     evaluation negatives per vertex so that it is a function of Z alone;
+ *   - the other spring-electrical models of Table 2 (Fruchterman-Reingold,
+ *     LinLog, ForceAtlas): attractive force magnitude t^2, log(1 + t) or t and
+ *     repulsive magnitude 1/t along the unit vector of z_u - z_other, pulling u
+ *     toward a neighbour and pushing it away from a negative; each is the
+ *     gradient of a stated potential, which serves as their loss;
+ *   - random-walk neighbourhoods (Algorithm 3, rForce2Vec of Section 3.3): the
+ *     distinct vertices a walk from u reaches, in the order first reached,
+ *     until k are found, a step bound is reached or the walk is stuck.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), written from that paper's definition;
@@ -39,10 +47,14 @@
 
 #define OR_SIGMOID 0
 #define OR_STUDENT_T 1
+#define OR_FR 2          /* Fruchterman-Reingold (Table 2) */
+#define OR_LINLOG 3      /* LinLog (Table 2) */
+#define OR_FORCEATLAS 4  /* ForceAtlas (Table 2) */
 
 #define TAG_PERM 1u
 #define TAG_NEG 2u
 #define TAG_EVAL 3u
+#define TAG_WALK 5u
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, from the SC'11 definition: ten rounds, each multiplying two
@@ -183,6 +195,38 @@ void or_eval_negatives(int64_t n, int32_t s, uint64_t seed, int32_t *W)
         }
 }
 
+/* Random-walk neighbourhood of u in epoch e (Algorithm 3): starting at u, each
+ * step moves to a uniformly chosen neighbour of the current vertex (step i
+ * draws Philox(e, u, i, TAG_WALK) and takes the neighbour at that uniform
+ * index of the current row); a vertex not yet in the set joins it (u itself
+ * included, if the walk comes back to it).  The paper's loop runs until the
+ * set holds k vertices, which never happens when fewer than k vertices are
+ * reachable, so the walk also stops after 4k steps or at a vertex with no
+ * neighbours.  list receives the set in the order its vertices were first
+ * reached; raw (may be NULL, room for 4k) every step's vertex, *nraw their
+ * number.  Returns the size of the set. */
+int32_t or_walk(const int64_t *rowptr, const int32_t *colidx, uint64_t seed, uint32_t epoch, int64_t u,
+                int32_t k, int32_t *list, int32_t *raw, int32_t *nraw)
+{
+    int32_t len = 0, steps = 0;
+    int64_t w = u;
+    while (len < k && steps < 4 * k) {
+        int64_t deg = rowptr[w + 1] - rowptr[w];
+        if (deg == 0) break;
+        uint32_t out[4];
+        philox_call(seed, epoch, (uint32_t)u, (uint32_t)steps, TAG_WALK, out);
+        int32_t next = colidx[rowptr[w] + or_uniform_index(out[0], out[1], deg)];
+        if (raw) raw[steps] = next;
+        ++steps;
+        int seen = 0;
+        for (int32_t j = 0; j < len && !seen; ++j) seen = list[j] == next;
+        if (!seen) list[len++] = next;
+        w = next;
+    }
+    if (nraw) *nraw = steps;
+    return len;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Per-pair forces (gradients of the per-vertex loss with respect to z_u, the
  * other row held fixed).  a = z_u, c = the other row.  Accumulated into g. */
@@ -210,8 +254,22 @@ static double sigmoid(double x)
     return ex / (1.0 + ex);
 }
 
-/* Attractive force: sigmoid Eq. 5 term, (sigma(a.c) - 1) c; Student-t Eq. 8
- * term times (a-c)/t, i.e. 2 (a - c) / (1 + |a-c|^2). */
+/* Magnitude, along the unit vector (a-c)/t, of the attractive gradient of the
+ * Table 2 models at distance t = |a - c|, the pull written as a positive
+ * gradient: t^2 (Fruchterman-Reingold), log(1 + t) (LinLog), t (ForceAtlas). */
+static double attraction_magnitude(int force, double t)
+{
+    switch (force) {
+    case OR_FR: return t * t;
+    case OR_LINLOG: return log1p(t);
+    default: return t; /* OR_FORCEATLAS */
+    }
+}
+
+/* Attractive force: sigmoid Eq. 5 term, (sigma(a.c) - 1) c; the distance-based
+ * models: magnitude times the unit vector (a-c)/t (0 when t = 0, where every
+ * magnitude above vanishes faster than t, except LinLog's, whose ratio
+ * log(1 + t)/t tends to 1: its limit is taken). */
 static void add_attraction(int d, int force, const double *a, const double *c, double *g,
                            int emul)
 {
@@ -226,7 +284,13 @@ static void add_attraction(int d, int force, const double *a, const double *c, d
             double df = input(a, i, emul) - input(c, i, emul);
             q += df * df;
         }
-        double coef = 2.0 / (1.0 + q);
+        double coef;
+        if (force == OR_STUDENT_T) {
+            coef = 2.0 / (1.0 + q); /* Eq. 8, 2t/(1+t^2), times 1/t */
+        } else {
+            double t = sqrt(q);
+            coef = t > 0.0 ? attraction_magnitude(force, t) / t : (force == OR_LINLOG ? 1.0 : 0.0);
+        }
         for (int i = 0; i < d; ++i) g[i] += coef * (input(a, i, emul) - input(c, i, emul));
     }
 }
@@ -250,7 +314,14 @@ static void add_repulsion(int d, int force, double eps, const double *a, const d
             q += df * df;
         }
         if (q + eps == 0.0) return;
-        double coef = -2.0 * (1.0 - eps) / ((q + eps) * (1.0 + q));
+        double coef;
+        if (force == OR_STUDENT_T) {
+            coef = -2.0 * (1.0 - eps) / ((q + eps) * (1.0 + q));
+        } else {
+            /* Table 2: magnitude 1/t pushing away, times (a-c)/t: -(a-c)/t^2,
+             * regularised as -(a-c)/(q+eps), the gradient of -log(q+eps)/2 */
+            coef = -1.0 / (q + eps);
+        }
         for (int i = 0; i < d; ++i) g[i] += coef * (input(a, i, emul) - input(c, i, emul));
     }
 }
@@ -276,6 +347,10 @@ static double softplus(double y)
     return (y > 0 ? y : 0.0) + log1p(exp(-fabs(y)));
 }
 
+/* The Table 2 models have no likelihood in the paper; their loss is the
+ * potential whose gradient the forces above are: attraction t^3/3 (FR),
+ * (1 + t) log(1 + t) - t (LinLog), t^2/2 (ForceAtlas); repulsion
+ * -log(q + eps)/2, taken as 0 where q + eps = 0 (as the force is). */
 double or_pair_loss(int d, int force, double eps, const double *a, const double *c,
                     int repulsive, int emul)
 {
@@ -289,7 +364,12 @@ double or_pair_loss(int d, int force, double eps, const double *a, const double 
         double df = input(a, i, emul) - input(c, i, emul);
         q += df * df;
     }
-    return repulsive ? log1p(q) - log(q + eps) : log1p(q);
+    if (force == OR_STUDENT_T) return repulsive ? log1p(q) - log(q + eps) : log1p(q);
+    if (repulsive) return q + eps == 0.0 ? 0.0 : -0.5 * log(q + eps);
+    double t = sqrt(q);
+    if (force == OR_FR) return t * t * t / 3.0;
+    if (force == OR_LINLOG) return (1.0 + t) * log1p(t) - t;
+    return 0.5 * q; /* OR_FORCEATLAS */
 }
 
 /* Loss of Eq. 2 summed over all vertices, with W[u*s+j] as the negatives of
@@ -335,6 +415,8 @@ void or_loss(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
  *   pairs    : if non-NULL, receives the number of pair evaluations
  *   k_begin, k_end : run only batches [k_begin, k_end) (a bounded sample of the
  *              epoch for timing); pass 0, -1 for the whole epoch.
+ *   walk_k   : 0: N(u) is u's row of the graph; k > 0: N(u) is the random-walk
+ *              neighbourhood of Algorithm 3 (or_walk) with walks of length k.
  *
  * Within a batch every gradient reads the batch-start state (Algorithm 2 reads
  * Z, Algorithm 1 applies the step after GradMinibatch returns); only the batch
@@ -342,7 +424,8 @@ void or_loss(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
 int or_epoch(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
              double *Z, int32_t b, int32_t s, int force, double eps, double lr,
              uint64_t seed, uint32_t epoch, int perm_mode, const int32_t *S_inject,
-             int emul, int nthreads, int64_t *pairs, int64_t k_begin, int64_t k_end)
+             int emul, int nthreads, int64_t *pairs, int64_t k_begin, int64_t k_end,
+             int32_t walk_k)
 {
     if (n <= 0 || d <= 0 || b <= 0 || s < 0) return 1;
     int64_t nb = (n + b - 1) / b;
@@ -350,7 +433,9 @@ int or_epoch(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
     int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *S = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s > 0 ? s : 1));
     double *G = (double *)malloc(sizeof(double) * (size_t)b * d);
-    if (!perm || !S || !G) { free(perm); free(S); free(G); return 2; }
+    int32_t *WL = (int32_t *)malloc(sizeof(int32_t) * (size_t)b * (walk_k > 0 ? walk_k : 1));
+    int32_t *WN = (int32_t *)malloc(sizeof(int32_t) * (size_t)b);
+    if (!perm || !S || !G || !WL || !WN) { free(perm); free(S); free(G); free(WL); free(WN); return 2; }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -376,8 +461,15 @@ int or_epoch(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
             const double *zu = Z + (size_t)u * d;
             double *g = G + (size_t)(p - lo) * d;
             for (int i = 0; i < d; ++i) g[i] = 0.0;
-            for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
-                add_attraction(d, force, zu, Z + (size_t)colidx[e] * d, g, emul);
+            if (walk_k > 0) {
+                int32_t *list = WL + (size_t)(p - lo) * walk_k;
+                WN[p - lo] = or_walk(rowptr, colidx, seed, epoch, u, walk_k, list, NULL, NULL);
+                for (int32_t j = 0; j < WN[p - lo]; ++j)
+                    add_attraction(d, force, zu, Z + (size_t)list[j] * d, g, emul);
+            } else {
+                for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e)
+                    add_attraction(d, force, zu, Z + (size_t)colidx[e] * d, g, emul);
+            }
             for (int32_t j = 0; j < s; ++j)
                 add_repulsion(d, force, eps, zu, Z + (size_t)S[j] * d, g, emul);
         }
@@ -387,13 +479,15 @@ int or_epoch(int64_t n, int32_t d, const int64_t *rowptr, const int32_t *colidx,
             double *zu = Z + (size_t)u * d;
             const double *g = G + (size_t)(p - lo) * d;
             for (int i = 0; i < d; ++i) zu[i] -= lr * g[i];
-            npairs += (rowptr[u + 1] - rowptr[u]) + s;
+            npairs += (walk_k > 0 ? WN[p - lo] : rowptr[u + 1] - rowptr[u]) + s;
         }
     }
     if (pairs) *pairs = npairs;
     free(perm);
     free(S);
     free(G);
+    free(WL);
+    free(WN);
     return 0;
 }
 

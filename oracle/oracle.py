@@ -3,7 +3,8 @@
 Functions follow the paper's Algorithm 1 (epoch driver: random partition into
 minibatches, one shared set of s negative samples per batch, Eq. 10 step),
 Algorithm 2 (per-vertex gradient from attractive and repulsive forces,
-Eqs. 5-6 sigmoid, Eqs. 8-9 Student-t) and the loss of Eq. 2.  See
+Eqs. 5-6 sigmoid, Eqs. 8-9 Student-t, and the models of Table 2),
+Algorithm 3 (random-walk neighbourhoods) and the loss of Eq. 2.  See
 f2v_oracle.c for the arithmetic.
 """
 from __future__ import annotations
@@ -19,11 +20,13 @@ __all__ = [
     "OracleParams", "build", "lib_path", "philox", "uniform_index", "partition",
     "perm_at", "pos_at", "negatives", "eval_negatives", "vertex_gradient",
     "pair_loss", "pair_losses", "bf16_round", "loss", "loss_arrays", "epoch", "run", "learning_rate", "num_threads",
-    "SIGMOID", "STUDENT_T",
+    "walk", "SIGMOID", "STUDENT_T", "FORCES",
 ]
 
 SIGMOID = 0
 STUDENT_T = 1
+# force model name -> code of the C oracle (Table 2's models after the two of Section 3.1)
+FORCES = {"sigmoid": 0, "student_t": 1, "fr": 2, "linlog": 3, "forceatlas": 4}
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "f2v_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
@@ -68,7 +71,9 @@ def _load():
     L.or_vertex_gradient.argtypes = [cint, cint, dbl, P, i32, P, i32, P, cint, P]
     L.or_loss.argtypes = [i64, i32, P, P, P, i32, P, cint, dbl, cint, cint, P]
     L.or_epoch.argtypes = [i64, i32, P, P, P, i32, i32, cint, dbl, dbl, u64, u32, cint, P,
-                           cint, cint, P, i64, i64]
+                           cint, cint, P, i64, i64, i32]
+    L.or_walk.argtypes = [P, P, u64, u32, i64, i32, P, P, P]
+    L.or_walk.restype = i32
     L.or_epoch.restype = cint
     L.or_pair_loss.argtypes = [cint, cint, dbl, P, P, cint, cint]
     L.or_pair_loss.restype = dbl
@@ -91,17 +96,19 @@ class OracleParams:
     d: int
     batch: int
     s: int
-    force: str = "sigmoid"          # "sigmoid" (sForce2Vec) or "student_t" (tForce2Vec)
-    eps: float = 1e-3               # Student-t repulsion regulariser
+    force: str = "sigmoid"          # "sigmoid" (sForce2Vec), "student_t" (tForce2Vec), or a
+                                    # Table 2 model: "fr", "linlog", "forceatlas"
+    eps: float = 1e-3               # repulsion regulariser of the distance-based models
     lr0: float = 0.02
     lr_schedule: str = "const"      # "const" or "linear"
     total_epochs: int = 1
     seed: int = 0
     perm_mode: str = "random"       # "random" or "identity"
+    walk_length: int = 0            # 0: N(u) = u's neighbours; k > 0: random walks (Algorithm 3)
 
     @property
     def force_code(self) -> int:
-        return SIGMOID if self.force == "sigmoid" else STUDENT_T
+        return FORCES[self.force]
 
     @staticmethod
     def from_dict(p: dict) -> "OracleParams":
@@ -165,17 +172,18 @@ def vertex_gradient(force: str, eps: float, zu, nbr_rows, neg_rows, emul: bool =
     nb = np.ascontiguousarray(np.asarray(nbr_rows, dtype=np.float64).reshape(-1, d))
     ng = np.ascontiguousarray(np.asarray(neg_rows, dtype=np.float64).reshape(-1, d))
     g = np.zeros(d, dtype=np.float64)
-    fc = SIGMOID if force == "sigmoid" else STUDENT_T
+    fc = FORCES[force]
     _load().or_vertex_gradient(d, fc, eps, _ptr(zu), nb.shape[0], _ptr(nb), ng.shape[0], _ptr(ng),
                                1 if emul else 0, _ptr(g))
     return g
 
 
 def pair_loss(force: str, eps: float, a, c, repulsive: bool, emul: bool = False) -> float:
-    """One term of Eq. 2: -log delta(a, c) for a neighbour, -log(1 - delta) for a negative."""
+    """One term of Eq. 2: -log delta(a, c) for a neighbour, -log(1 - delta) for a
+    negative; for a Table 2 model the potential whose gradient its force is."""
     a = np.ascontiguousarray(a, dtype=np.float64)
     c = np.ascontiguousarray(c, dtype=np.float64)
-    fc = SIGMOID if force == "sigmoid" else STUDENT_T
+    fc = FORCES[force]
     return float(_load().or_pair_loss(a.shape[0], fc, eps, _ptr(a), _ptr(c), 1 if repulsive else 0,
                                       1 if emul else 0))
 
@@ -204,7 +212,7 @@ def loss_arrays(n, d, rowptr, colidx, Z, s, W, force, eps, emul=False, threads=0
     colidx = np.ascontiguousarray(colidx, dtype=np.int32)
     W = np.ascontiguousarray(W, dtype=np.int32)
     out = np.zeros(3, dtype=np.float64)
-    fc = SIGMOID if force == "sigmoid" else STUDENT_T
+    fc = FORCES[force]
     L.or_loss(n, d, _ptr(rowptr), _ptr(colidx), _ptr(Z), s, _ptr(W), fc, eps,
               1 if emul else 0, threads, _ptr(out))
     return out
@@ -216,6 +224,20 @@ def loss(graph, Z, p: OracleParams, emul: bool = False, threads: int = 0) -> np.
     W = eval_negatives(graph.n, p.s, p.seed)
     return loss_arrays(graph.n, p.d, graph.rowptr, graph.colidx, Z, p.s, W, p.force, p.eps,
                        emul, threads)
+
+
+def walk(graph, seed: int, epoch_idx: int, u: int, k: int, raw: bool = False):
+    """Random-walk neighbourhood of u in an epoch (Algorithm 3): the distinct
+    vertices reached, in the order first reached (at most k; the walk stops
+    after 4k steps or at a vertex without neighbours).  With raw=True also
+    every step's vertex."""
+    rowptr = np.ascontiguousarray(graph.rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(graph.colidx, dtype=np.int32)
+    lst = np.empty(max(k, 1), dtype=np.int32)
+    steps = np.empty(max(4 * k, 1), dtype=np.int32)
+    nraw = np.zeros(1, dtype=np.int32)
+    m = _load().or_walk(_ptr(rowptr), _ptr(colidx), seed, epoch_idx, u, k, _ptr(lst), _ptr(steps), _ptr(nraw))
+    return (lst[:m].copy(), steps[:nraw[0]].copy()) if raw else lst[:m].copy()
 
 
 def learning_rate(p: OracleParams, epoch_idx: int) -> float:
@@ -243,7 +265,7 @@ def epoch(graph, Z, epoch_idx: int, p: OracleParams, *, emul: bool = False,
                     p.force_code, p.eps, lr, p.seed, epoch_idx,
                     1 if p.perm_mode == "identity" else 0,
                     _ptr(sinj) if sinj is not None else None,
-                    1 if emul else 0, threads, _ptr(pairs), kb, ke)
+                    1 if emul else 0, threads, _ptr(pairs), kb, ke, p.walk_length)
     if rc != 0:
         raise RuntimeError("oracle epoch failed with code %d" % rc)
     return (Zc, int(pairs[0])) if return_pairs else Zc
