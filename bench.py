@@ -148,9 +148,11 @@ def cpu_baseline(g, Z0, p, seconds_target: float = 12.0) -> dict:
     op = oracle.OracleParams.from_dict(p)
     Z = np.asarray(Z0, dtype=np.float64)
     nb = (g.n + op.batch - 1) // op.batch
-    pairs, dt, batches = time_oracle(g, Z, op, nb, seconds_target, 0)
+    cores = oracle.num_threads()
+    pairs, dt, batches = time_oracle(g, Z, op, nb, seconds_target, cores)
     pairs1, dt1, batches1 = time_oracle(g, Z, op, nb, seconds_target / 4, 1)
-    return {"value": pairs / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+    oracle.set_num_threads(cores)
+    return {"value": pairs / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(), "single_thread_value": pairs1 / dt1,
             "sample": f"first {batches} of {nb} batches of epoch 0 ({pairs} pair updates, "
                       f"{dt:.1f} s, FP64, OpenMP over the batch's vertices); single thread: first "

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "CSRGraph", "csr_from_edges", "erdos_renyi", "chung_lu", "sbm",
     "random_geometric", "star", "path", "bfs_ball", "init_embedding",
-    "relabel", "workload",
+    "relabel", "workload", "sbm_blocks",
 ]
 
 
@@ -149,6 +149,19 @@ def sbm(n: int, blocks: int, c_in: float, c_out: float, seed: int, *,
     d_out = ((s_out // bs + d_off) % blocks) * bs + rng.integers(0, bs, size=m_out)
     g = csr_from_edges(n, np.concatenate([s_in, s_out]), np.concatenate([d_in, d_out]))
     return relabel(g, seed + 104729) if do_relabel else g
+
+
+def sbm_blocks(n: int, blocks: int, seed: int, *, do_relabel: bool = True) -> np.ndarray:
+    """Planted block of every vertex of sbm(n, blocks, ..., seed) (int64 [n]),
+    with the same relabelling."""
+    bs = n // blocks
+    blk = np.arange(n, dtype=np.int64) // bs
+    if not do_relabel:
+        return blk
+    new_id = np.random.default_rng(seed + 104729).permutation(n).astype(np.int64)
+    out = np.empty(n, dtype=np.int64)
+    out[new_id] = blk
+    return out
 
 
 def random_geometric(n: int, avg_deg: float, seed: int) -> CSRGraph:

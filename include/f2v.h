@@ -61,7 +61,21 @@ typedef enum {
     F2V_E_UNSUPPORTED = 8  /* valid request the library does not implement */
 } f2v_status;
 
-typedef enum { F2V_FORCE_SIGMOID = 0, F2V_FORCE_STUDENT_T = 1 } f2v_force;
+/* Force models.  SIGMOID: Eqs. 3, 5, 6.  STUDENT_T: Eqs. 7-9 along the unit
+ * vector of z_u - z_v.  The spring-electrical models of Table 2: attraction
+ * of magnitude t^2 (FR, Fruchterman-Reingold), log(1 + t) (LINLOG) or t
+ * (FORCEATLAS) pulling u toward a neighbour, repulsion of magnitude 1/t
+ * pushing it away from a negative, t = |z_u - z_other|; the repulsion is
+ * regularised as the gradient of -log(q + eps)/2, q = t^2 (0 at q + eps = 0).
+ * Their loss (f2v_loss) is the potential whose gradient the forces are:
+ * t^3/3, (1 + t) log(1 + t) - t or t^2/2, and -log(q + eps)/2. */
+typedef enum {
+    F2V_FORCE_SIGMOID = 0,
+    F2V_FORCE_STUDENT_T = 1,
+    F2V_FORCE_FR = 2,
+    F2V_FORCE_LINLOG = 3,
+    F2V_FORCE_FORCEATLAS = 4
+} f2v_force;
 typedef enum { F2V_FP32 = 0, F2V_BF16 = 1 } f2v_precision;
 typedef enum { F2V_LR_CONST = 0, F2V_LR_LINEAR = 1 } f2v_lr_schedule;
 typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
@@ -75,8 +89,18 @@ typedef enum { F2V_PERM_RANDOM = 0, F2V_PERM_IDENTITY = 1 } f2v_perm_mode;
  * STRICT: one launch per batch, batches separated by the stream order.
  * DYNAMIC: as DATAFLOW, but running waves claim work in batch order from a
  *   counter, so the launch needs no co-residency and its grid is sized to the
- *   graph; for many concurrent jobs on one device (the server). */
-typedef enum { F2V_SCHED_DATAFLOW = 0, F2V_SCHED_STRICT = 1, F2V_SCHED_DYNAMIC = 2 } f2v_schedule;
+ *   graph; for many concurrent jobs on one device (the server).
+ * HOGWILD: the relaxed, asynchronous variant that Section 3.2 contrasts with
+ *   the synchronous one: one embedding buffer updated in place, and a row is
+ *   read in whatever state it is when read (no waits for earlier batches),
+ *   so results depend on timing and are not reproducible; a throughput study,
+ *   not the paper's method. */
+typedef enum {
+    F2V_SCHED_DATAFLOW = 0,
+    F2V_SCHED_STRICT = 1,
+    F2V_SCHED_DYNAMIC = 2,
+    F2V_SCHED_HOGWILD = 3
+} f2v_schedule;
 
 typedef struct {
     int64_t n;            /* vertices, >= 1, < 2^29 - 1 */
@@ -108,14 +132,32 @@ typedef struct {
                              depend on it. */
     int32_t fan_in;       /* fan-in of the fixed-order tree that combines a
                              split row's partial sums, 4 .. 64; 0 = default 8 */
+    int32_t walk_length;  /* 0: N(u) is u's CSR row.  k in 1 .. 64: N(u) is the
+                             random-walk neighbourhood of Algorithm 3
+                             (rForce2Vec), drawn afresh every epoch: the
+                             distinct vertices a walk from u reaches, in the
+                             order first reached (step i of epoch e from u
+                             draws Philox(e, u, i, 5) and moves to the
+                             neighbour at that uniform index of the current
+                             row), until k are found, 4k steps are taken or
+                             the walk reaches a vertex without neighbours.
+                             f2v_loss still sums over the CSR rows. */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
  * eps = 1e-3, random partition, dataflow schedule, chunk 0 (by size), seed 0,
- * late_window -1 and fan_in 0 (defaults).  n, nnz and d must still be set. */
+ * late_window -1 and fan_in 0 (defaults), walk_length 0 (CSR rows).  n, nnz
+ * and d must still be set. */
 void f2v_default_params(f2v_params *p);
+
+/* Host only.  Step size eta_e of epoch `epoch` (Algorithm 1 fixes only the
+ * initial eta): lr0, or lr0 (1 - epoch / total_epochs) under the linear
+ * schedule.  F2V_E_INVALID_ARG for epoch < 0 and, under the linear schedule,
+ * for epoch >= total_epochs (eta would be <= 0: no step, or ascent);
+ * f2v_epoch refuses such an epoch the same way. */
+f2v_status f2v_step_size(const f2v_params *p, int32_t epoch, float *eta);
 
 /* Host only.  Bytes of device workspace the context needs (a bound from
  * n, nnz, d, b, s, precision and chunk; independent of the graph's degrees). */
@@ -183,6 +225,15 @@ f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_m
                          int32_t *d_perm, void *stream);
 f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch,
                          int32_t *d_S, void *stream);
+
+/* Device copy of the random-walk neighbourhoods of epoch e (walk mode,
+ * Algorithm 3; see walk_length): for every vertex u, d_len[u] <= k and its
+ * walk's distinct vertices in the order first reached at d_list[u*k .. u*k +
+ * d_len[u]).  d_rowptr int64[n+1] and d_colidx int32[rowptr[n]] are the CSR
+ * (device), d_list int32[n*k], d_len int32[n] (device).  1 <= k <= 64.
+ * Asynchronous on `stream`. */
+f2v_status f2v_walks(const int64_t *d_rowptr, const int32_t *d_colidx, int64_t n, int32_t k, uint64_t seed,
+                     int32_t epoch, int32_t *d_list, int32_t *d_len, void *stream);
 
 /* A random initial embedding on the device: count floats uniform on
  * [-scale, scale) (the method starts from a random Z; a U[-0.5, 0.5) start is

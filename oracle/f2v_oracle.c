@@ -499,6 +499,15 @@ double or_learning_rate(double lr0, int schedule, int32_t epoch, int32_t total_e
     return lr0;
 }
 
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -20,7 +20,7 @@ __all__ = [
     "OracleParams", "build", "lib_path", "philox", "uniform_index", "partition",
     "perm_at", "pos_at", "negatives", "eval_negatives", "vertex_gradient",
     "pair_loss", "pair_losses", "bf16_round", "loss", "loss_arrays", "epoch", "run", "learning_rate", "num_threads",
-    "walk", "SIGMOID", "STUDENT_T", "FORCES",
+    "walk", "set_num_threads", "SIGMOID", "STUDENT_T", "FORCES",
 ]
 
 SIGMOID = 0
@@ -82,6 +82,7 @@ def _load():
     L.or_learning_rate.argtypes = [dbl, cint, i32, i32]
     L.or_learning_rate.restype = dbl
     L.or_num_threads.restype = cint
+    L.or_set_num_threads.argtypes = [cint]
     _lib = L
     return L
 
@@ -118,6 +119,11 @@ class OracleParams:
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later calls that pass threads=0 (OpenMP)."""
+    _load().or_set_num_threads(int(n))
 
 
 def philox(ctr, key) -> np.ndarray:

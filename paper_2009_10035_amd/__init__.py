@@ -14,7 +14,7 @@ import torch
 from ._binding import (EXPORTS, F2VError, Params, check, footprint, load, make_params, workspace_size)
 
 __all__ = ["Trainer", "F2VError", "Params", "make_params", "workspace_size", "footprint", "partition",
-           "negatives", "random_embedding", "load", "EXPORTS"]
+           "negatives", "walks", "random_embedding", "load", "EXPORTS"]
 
 
 def _stream_handle(device) -> int:
@@ -166,6 +166,21 @@ def random_embedding(n: int, d: int, seed: int, scale: float = 0.5, device="cuda
     check(load().f2v_random_embedding(out.data_ptr() if out.numel() else None, n * d, seed, scale,
                                       _stream_handle(out.device)))
     return out
+
+
+def walks(rowptr: torch.Tensor, colidx: torch.Tensor, k: int, seed: int, epoch: int):
+    """Random-walk neighbourhoods of an epoch (Algorithm 3) on the device:
+    (list int32 [n, k], length int32 [n]); row u holds its first length[u]
+    entries."""
+    _require_device(rowptr, torch.int64, "rowptr")
+    _require_device(colidx, torch.int32, "colidx")
+    n = rowptr.numel() - 1
+    lst = torch.full((n, k), -1, dtype=torch.int32, device=rowptr.device)
+    ln = torch.empty(n, dtype=torch.int32, device=rowptr.device)
+    col = colidx if colidx.numel() else lst
+    check(load().f2v_walks(rowptr.data_ptr(), col.data_ptr(), n, k, seed, epoch, lst.data_ptr(), ln.data_ptr(),
+                           _stream_handle(rowptr.device)))
+    return lst, ln
 
 
 def negatives(n: int, batch: int, s: int, seed: int, epoch: int, device="cuda") -> torch.Tensor:

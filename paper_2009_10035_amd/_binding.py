@@ -20,15 +20,16 @@ EXPORTS = (
     "f2v_vertex_trace", "f2v_footprint", "f2v_server_create", "f2v_server_submit",
     "f2v_server_flush", "f2v_server_poll", "f2v_server_query", "f2v_server_drain",
     "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding", "f2v_health",
+    "f2v_walks", "f2v_step_size",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",
           5: "F2V_E_STATE", 6: "F2V_E_TIMEOUT", 7: "F2V_E_BUSY", 8: "F2V_E_UNSUPPORTED"}
-FORCE = {"sigmoid": 0, "student_t": 1}
+FORCE = {"sigmoid": 0, "student_t": 1, "fr": 2, "linlog": 3, "forceatlas": 4}
 PRECISION = {"fp32": 0, "bf16": 1}
 LR_SCHEDULE = {"const": 0, "linear": 1}
 PERM = {"random": 0, "identity": 1}
-SCHEDULE = {"dataflow": 0, "strict": 1, "dynamic": 2}
+SCHEDULE = {"dataflow": 0, "strict": 1, "dynamic": 2, "hogwild": 3}
 
 
 class F2VError(RuntimeError):
@@ -46,7 +47,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("lr_schedule", ctypes.c_int32), ("lr0", ctypes.c_float),
         ("eps", ctypes.c_float), ("total_epochs", ctypes.c_int32), ("perm_mode", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("chunk", ctypes.c_int32), ("seed", ctypes.c_uint64),
-        ("late_window", ctypes.c_int32), ("fan_in", ctypes.c_int32),
+        ("late_window", ctypes.c_int32), ("fan_in", ctypes.c_int32), ("walk_length", ctypes.c_int32),
     ]
 
 
@@ -113,6 +114,10 @@ def load(build_if_missing: bool = True):
     L.f2v_server_query.restype = st
     L.f2v_random_embedding.argtypes = [P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, P]
     L.f2v_random_embedding.restype = st
+    L.f2v_walks.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, P, P, P]
+    L.f2v_walks.restype = st
+    L.f2v_step_size.argtypes = [PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
+    L.f2v_step_size.restype = st
     L.f2v_health.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
     L.f2v_health.restype = st
     L.f2v_server_last_error.argtypes = [P]
@@ -131,7 +136,7 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
                 precision: str = "fp32", lr0: float = 0.02, lr_schedule: str = "const",
                 eps: float = 1e-3, total_epochs: int = 1, perm_mode: str = "random",
                 schedule: str = "dataflow", chunk: int | None = None, seed: int = 0,
-                late_window: int | None = None, fan_in: int | None = None) -> Params:
+                late_window: int | None = None, fan_in: int | None = None, walk_length: int = 0) -> Params:
     p = Params()
     load().f2v_default_params(ctypes.byref(p))
     p.n, p.nnz, p.d, p.batch, p.s = n, nnz, d, batch, s
@@ -146,6 +151,7 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
         p.late_window = late_window
     if fan_in is not None:
         p.fan_in = fan_in
+    p.walk_length = walk_length
     return p
 
 

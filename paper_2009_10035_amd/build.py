@@ -16,9 +16,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libf2v.so")
-# The gather-ceiling probe (a measurement tool, kept out of libf2v.so).
-PROBE_SRC = "probe_gather.hip"
-PROBE_LIB = os.path.join(HERE, "libf2v_probe.so")
 ARCH = os.environ.get("F2V_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = [
@@ -61,18 +58,16 @@ def _compile(src: str) -> str:
 
 
 def build(jobs: int | None = None, verbose: bool = True) -> str:
-    """Compile all sources (always) and link libf2v.so and the probe library;
-    returns the path of libf2v.so."""
+    """Compile all sources (always) and link libf2v.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1), 16)
     t0 = time.time()
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES + [PROBE_SRC]))
-    for lib, parts in ((LIB, objs[:-1]), (PROBE_LIB, objs[-1:])):
-        tmp = lib + ".tmp%d" % os.getpid()
-        cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *parts]
-        subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(tmp, lib)
+        objs = list(ex.map(_compile, SOURCES))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    subprocess.run(cmd, check=True, capture_output=True)
+    os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s", file=sys.stderr)
     return LIB

@@ -54,7 +54,7 @@ thread_local std::string g_error;
 
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, negs, wreal,
-      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, health,
+      ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, health, wcol, wlen,
       csr_flag, init_rec, scan_scratch, scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket,
       total;
   int64_t nb, tmap_cap, hub_slot_cap;
@@ -63,7 +63,9 @@ struct Layout {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 int32_t chunk_of(const f2v_params& p) {
-  return p.chunk > 0 ? p.chunk : (p.n >= kLargeGraph ? kLargeChunk : kSmallChunk);
+  const int32_t c = p.chunk > 0 ? p.chunk : (p.n >= kLargeGraph ? kLargeChunk : kSmallChunk);
+  // walk lists are never split
+  return p.walk_length > c ? p.walk_length : c;
 }
 
 Layout layout_of(const f2v_params& p) {
@@ -109,6 +111,8 @@ Layout layout_of(const f2v_params& p) {
   L.hub_part = take(size_t(L.hub_slot_cap) * d * 4);
   L.err = take(4 * f2v::kErrWords);
   L.health = take(4 * f2v::kHealthWords);
+  L.wcol = take(size_t(n) * (p.walk_length > 0 ? p.walk_length : 0) * 4);
+  L.wlen = take(p.walk_length > 0 ? size_t(n) * 4 : 0);
   L.csr_flag = take(4);
   L.init_rec = take(3 * 8);
   L.scan_scratch = take(size_t((n + 1023) / 1024 + 1) * 8);
@@ -143,8 +147,10 @@ f2v_status validate(const f2v_params* p, std::string* msg) {
                     " (d % 4 == 0 up to 1024, d % 4 == 2 up to 128, odd d up to 64; bf16 even d)");
   if (p->batch < 1) return fail(msg, F2V_E_INVALID_ARG, "batch must be >= 1");
   if (p->s < 0 || p->s > 64) return fail(msg, F2V_E_INVALID_ARG, "s must be in [0, 64]");
-  if (p->force != F2V_FORCE_SIGMOID && p->force != F2V_FORCE_STUDENT_T)
-    return fail(msg, F2V_E_INVALID_ARG, "force must be sigmoid or Student-t");
+  if (p->force < F2V_FORCE_SIGMOID || p->force > F2V_FORCE_FORCEATLAS)
+    return fail(msg, F2V_E_INVALID_ARG, "force must be sigmoid, Student-t, FR, LinLog or ForceAtlas");
+  if (p->walk_length < 0 || p->walk_length > f2v::kMaxWalk)
+    return fail(msg, F2V_E_INVALID_ARG, "walk_length must be in [0, 64]");
   if (!std::isfinite(p->lr0) || !(p->lr0 > 0.0f)) return fail(msg, F2V_E_INVALID_ARG, "lr0 must be finite and > 0");
   if (!std::isfinite(p->eps) || p->eps < 0.0f || p->eps >= 1.0f)
     return fail(msg, F2V_E_INVALID_ARG, "eps must be in [0, 1)");
@@ -155,8 +161,8 @@ f2v_status validate(const f2v_params* p, std::string* msg) {
   if (p->perm_mode != F2V_PERM_RANDOM && p->perm_mode != F2V_PERM_IDENTITY)
     return fail(msg, F2V_E_INVALID_ARG, "perm_mode must be random or identity");
   if (p->schedule != F2V_SCHED_DATAFLOW && p->schedule != F2V_SCHED_STRICT &&
-      p->schedule != F2V_SCHED_DYNAMIC)
-    return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow, strict or dynamic");
+      p->schedule != F2V_SCHED_DYNAMIC && p->schedule != F2V_SCHED_HOGWILD)
+    return fail(msg, F2V_E_INVALID_ARG, "schedule must be dataflow, strict, dynamic or hogwild");
   if (p->chunk < 0 || p->chunk > kMaxChunk) return fail(msg, F2V_E_INVALID_ARG, "chunk must be in [0, 2^20]");
   if (p->late_window > (1 << 20)) return fail(msg, F2V_E_INVALID_ARG, "late_window must be at most 2^20");
   if (p->fan_in != 0 && (p->fan_in < 4 || p->fan_in > 64))
@@ -265,6 +271,7 @@ void f2v_default_params(f2v_params* p) {
   p->seed = 0;
   p->late_window = -1;
   p->fan_in = 0;
+  p->walk_length = 0;
 }
 
 f2v_status f2v_footprint(const f2v_params* p, size_t* bytes) {
@@ -272,6 +279,17 @@ f2v_status f2v_footprint(const f2v_params* p, size_t* bytes) {
   if (st != F2V_OK) return st;
   if (!bytes) return fail(nullptr, F2V_E_INVALID_ARG, "bytes is NULL");
   *bytes = size_t(p->n + 1) * 8 + size_t(p->nnz) * 4 + size_t(p->n) * p->d * 4 + layout_of(*p).total;
+  return F2V_OK;
+}
+
+f2v_status f2v_step_size(const f2v_params* p, int32_t epoch, float* eta) {
+  f2v_status st = validate(p, nullptr);
+  if (st != F2V_OK) return st;
+  if (!eta) return fail(nullptr, F2V_E_INVALID_ARG, "eta is NULL");
+  if (epoch < 0) return fail(nullptr, F2V_E_INVALID_ARG, "epoch must be >= 0");
+  if (p->lr_schedule == F2V_LR_LINEAR && epoch >= p->total_epochs)
+    return fail(nullptr, F2V_E_INVALID_ARG, "epoch must be < total_epochs under the linear schedule");
+  *eta = epoch_lr(*p, epoch);
   return F2V_OK;
 }
 
@@ -428,8 +446,9 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   const int64_t hub_total = rec[1], nsplit = rec[2];
   if (hub_total > L.hub_slot_cap) return bail(F2V_E_INVALID_ARG, "split-row slots exceed the workspace bound");
   if (nsplit < 0 || nsplit > p->n) return bail(F2V_E_INVALID_ARG, "split-row count out of range");
-  c->hub_total = hub_total;
-  c->nsplit = nsplit;
+  // walk mode: every list is at most walk_length <= chunk entries, nothing is split
+  c->hub_total = p->walk_length > 0 ? 0 : hub_total;
+  c->nsplit = p->walk_length > 0 ? 0 : nsplit;
   *out = c;
   return F2V_OK;
 }
@@ -438,6 +457,8 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
   if (epoch < 0) return fail(&c->err, F2V_E_INVALID_ARG, "epoch must be >= 0");
   const f2v_params& p = c->p;
+  if (p.lr_schedule == F2V_LR_LINEAR && epoch >= p.total_epochs)
+    return fail(&c->err, F2V_E_INVALID_ARG, "epoch must be < total_epochs under the linear schedule");
   const Layout& L = c->L;
   const hipStream_t s = c->stream;
   const bool bf16 = p.precision == F2V_BF16;
@@ -451,6 +472,9 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   sa.word = c->at<uint32_t>(L.word);
   sa.bat = L.nb <= 65536 ? c->at<uint16_t>(L.bat) : nullptr;
   sa.split_ids = c->at<int32_t>(L.split_ids);
+  sa.walk_k = p.walk_length;
+  sa.wcol = p.walk_length > 0 ? c->at<int32_t>(L.wcol) : nullptr;
+  sa.wlen = p.walk_length > 0 ? c->at<int32_t>(L.wlen) : nullptr;
   sa.pcol = c->at<int32_t>(L.pcol);
   sa.ecnt = c->at<int32_t>(L.ecnt);
   sa.uoff = c->at<int32_t>(L.uoff);
@@ -490,13 +514,18 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   EpochArgs A{};
   A.colidx = c->colidx;
   A.pcol = sa.pcol;
+  A.wcol = sa.wcol;
+  // the relaxed variant reads and writes one buffer in place
+  const bool hogwild = p.schedule == F2V_SCHED_HOGWILD;
+  const int next = hogwild ? c->cur : 1 - c->cur;
+  A.relaxed = hogwild ? 1 : 0;
   if (bf16) {
     A.zc = c->bbuf[c->cur];
-    A.zn = c->bbuf[1 - c->cur];
+    A.zn = c->bbuf[next];
     A.master = c->z_user;
   } else {
     A.zc = c->zbuf[c->cur];
-    A.zn = c->zbuf[1 - c->cur];
+    A.zn = c->zbuf[next];
     A.master = nullptr;
   }
   A.word = sa.word;
@@ -537,7 +566,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
     A.claim = 1;
     void* args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
-  } else if (p.schedule == F2V_SCHED_DATAFLOW) {
+  } else if (p.schedule == F2V_SCHED_DATAFLOW || hogwild) {
     // static round robin; the kernel checks co-residency and claims if needed
     A.strict_batch = -1;
     void* args[] = {&A};
@@ -562,7 +591,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->timed = true;
   }
-  c->cur = 1 - c->cur;
+  c->cur = next;
   return F2V_OK;
 }
 
@@ -704,6 +733,18 @@ f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_m
   hipError_t e = f2v::launch_partition(n, seed, static_cast<uint32_t>(epoch), perm_mode == F2V_PERM_IDENTITY,
                                        d_perm, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("partition: ") + hipGetErrorString(e));
+  return F2V_OK;
+}
+
+f2v_status f2v_walks(const int64_t* d_rowptr, const int32_t* d_colidx, int64_t n, int32_t k, uint64_t seed,
+                     int32_t epoch, int32_t* d_list, int32_t* d_len, void* stream) {
+  if (n < 1 || n >= (int64_t{1} << 29) - 1) return fail(nullptr, F2V_E_INVALID_ARG, "n out of range");
+  if (k < 1 || k > f2v::kMaxWalk) return fail(nullptr, F2V_E_INVALID_ARG, "k must be in [1, 64]");
+  if (epoch < 0) return fail(nullptr, F2V_E_INVALID_ARG, "epoch must be >= 0");
+  if (!d_rowptr || !d_colidx || !d_list || !d_len) return fail(nullptr, F2V_E_INVALID_ARG, "NULL device pointer");
+  hipError_t e = f2v::launch_walks(d_rowptr, d_colidx, n, k, seed, static_cast<uint32_t>(epoch), d_list, d_len,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("walks: ") + hipGetErrorString(e));
   return F2V_OK;
 }
 

@@ -13,7 +13,7 @@ namespace f2v {
 // multipliers, returns their low halves as words 3 and 1 and their high halves
 // xor-ed with the other counter word and the round key as words 2 and 0; the
 // key advances by two Weyl increments per round.
-enum : uint32_t { kTagPerm = 1, kTagNeg = 2, kTagEval = 3 };
+enum : uint32_t { kTagPerm = 1, kTagNeg = 2, kTagEval = 3, kTagWalk = 5 };
 constexpr int kFeistelRounds = 12;
 
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -300,38 +300,70 @@ __device__ __forceinline__ float group_sum8_scatter(const float (&p)[8]) {
 
 // ---------------------------------------------------------------------------
 // Per-pair forces: gradient of the per-vertex loss with respect to z_u.
-// `dotq` is z_u . z_v (sigmoid) or |z_u - z_v|^2 (Student-t), summed over the
-// whole row.  The returned scalar multiplies z_v (sigmoid) or z_u - z_v
-// (Student-t).
-enum Force : int32_t { kSigmoid = 0, kStudentT = 1 };
+// `dotq` is z_u . z_v (sigmoid) or |z_u - z_v|^2 (the distance-based models),
+// summed over the whole row.  The returned scalar multiplies z_v (sigmoid) or
+// z_u - z_v (distance-based models).
+enum Force : int32_t { kSigmoid = 0, kStudentT = 1, kFR = 2, kLinLog = 3, kForceAtlas = 4 };
 
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// attraction, Eq. 5 (sigmoid: sigma(x) - 1) and Eq. 8 along the unit vector
-// (Student-t: 2 / (1 + q))
+// attraction: Eq. 5 (sigmoid: sigma(x) - 1); the distance-based models'
+// magnitude along the unit vector (z_u - z_v)/t, divided by t: Eq. 8,
+// 2 / (1 + q); Table 2's pulls t^2 (Fruchterman-Reingold) -> t, log(1 + t)
+// (LinLog) -> log(1 + t)/t (1 at t = 0), t (ForceAtlas) -> 1
 __device__ __forceinline__ float attract_coef(int32_t force, float dotq) {
-  return force == kSigmoid ? -sigmoidf_(-dotq) : 2.0f / (1.0f + dotq);
+  switch (force) {
+    case kSigmoid: return -sigmoidf_(-dotq);
+    case kStudentT: return 2.0f / (1.0f + dotq);
+    case kFR: return sqrtf(dotq);
+    case kLinLog: {
+      const float t = sqrtf(dotq);
+      return t > 0.0f ? log1pf(t) / t : 1.0f;
+    }
+    default: return 1.0f;  // kForceAtlas
+  }
 }
-// repulsion, Eq. 6 (sigma(x)) and the eps-regularised Eq. 9 along the unit
-// vector (-2 (1 - eps) / ((q + eps)(1 + q)), 0 when q + eps = 0)
+// repulsion: Eq. 6 (sigma(x)); the eps-regularised Eq. 9 along the unit
+// vector (-2 (1 - eps) / ((q + eps)(1 + q))); Table 2's push 1/t along the
+// unit vector, -1 / (q + eps); both 0 when q + eps = 0
 __device__ __forceinline__ float repulse_coef(int32_t force, float dotq, float eps) {
   if (force == kSigmoid) return sigmoidf_(dotq);
-  const float den = (dotq + eps) * (1.0f + dotq);
-  return den == 0.0f ? 0.0f : -2.0f * (1.0f - eps) / den;
+  if (force == kStudentT) {
+    const float den = (dotq + eps) * (1.0f + dotq);
+    return den == 0.0f ? 0.0f : -2.0f * (1.0f - eps) / den;
+  }
+  const float den = dotq + eps;
+  return den == 0.0f ? 0.0f : -1.0f / den;
 }
 
-// Loss terms of Eq. 2 (FP32): -log delta for a neighbour, -log(1 - delta) for
-// a negative.  Sigmoid: softplus(-x), softplus(x).  Student-t: log(1 + q) and
-// log((1 + q) / (q + eps)), the latter as log1p((1 - eps) / (q + eps)).
+// Loss terms (FP32).  Eq. 2: -log delta for a neighbour, -log(1 - delta) for
+// a negative; sigmoid: softplus(-x), softplus(x); Student-t: log(1 + q) and
+// log((1 + q) / (q + eps)), the latter as log1p((1 - eps) / (q + eps)).  The
+// Table 2 models: the potential whose gradient the force is, t^3/3
+// (Fruchterman-Reingold), (1 + t) log(1 + t) - t (LinLog; its Taylor series
+// below t = 0.01, where the difference cancels), q/2 (ForceAtlas); repulsion
+// -log(q + eps)/2 (0 where q + eps = 0).
 __device__ __forceinline__ float softplusf_(float y) {
   return fmaxf(y, 0.0f) + log1pf(expf(-fabsf(y)));
 }
 __device__ __forceinline__ float attract_loss(int32_t force, float dotq) {
-  return force == kSigmoid ? softplusf_(-dotq) : log1pf(dotq);
+  switch (force) {
+    case kSigmoid: return softplusf_(-dotq);
+    case kStudentT: return log1pf(dotq);
+    case kFR: return dotq * sqrtf(dotq) * (1.0f / 3.0f);
+    case kLinLog: {
+      const float t = sqrtf(dotq);
+      if (t < 0.01f) return t * t * (0.5f - t * (1.0f / 6.0f - t * (1.0f / 12.0f)));
+      return (1.0f + t) * log1pf(t) - t;
+    }
+    default: return 0.5f * dotq;  // kForceAtlas
+  }
 }
 __device__ __forceinline__ float repulse_loss(int32_t force, float dotq, float eps) {
   if (force == kSigmoid) return softplusf_(dotq);
-  return log1pf((1.0f - eps) / (dotq + eps));
+  if (force == kStudentT) return log1pf((1.0f - eps) / (dotq + eps));
+  const float den = dotq + eps;
+  return den == 0.0f ? 0.0f : -0.5f * logf(den);
 }
 
 }  // namespace f2v

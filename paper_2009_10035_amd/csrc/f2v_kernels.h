@@ -58,6 +58,10 @@ constexpr int32_t kUnitWhole = 1;
 constexpr int32_t kUnitEarly = 2;
 constexpr int32_t kUnitLate = 4;
 constexpr int32_t kUnitReordered = 8;   // list read from the reordered copy
+constexpr int32_t kUnitWalk = 16;       // list read from the epoch's random-walk lists
+
+// Longest random walk (Algorithm 3) a context accepts, in distinct vertices.
+constexpr int32_t kMaxWalk = 64;
 
 // One work unit of an epoch: len list entries from offset beg of vertex u's
 // row (in the CSR or its reordered copy).  Early units: chunk c of the nch
@@ -89,6 +93,7 @@ enum WaveStat { kStatCycles = 0, kStatWaitCycles, kStatCombineCycles, kStatGroup
 struct EpochArgs {
   const int32_t* colidx;    // [nnz]
   const int32_t* pcol;      // [nnz] split rows' lists, early part then late part
+  const int32_t* wcol;      // walk mode: [n][walk_k] each vertex's walk neighbourhood
   const void* zc;           // rows read this epoch: float or bf16 [n][d]
   void* zn;                 // rows written this epoch (same type) [n][d]
   float* master;            // BF16 form: FP32 master rows, updated in place
@@ -123,6 +128,8 @@ struct EpochArgs {
   int32_t late_window;      // batches before a unit's own whose rows are taken last
   int32_t hold;             // >= 0: this vertex's row is written but never published (a
                             // host-forced stall, to exercise the wait bound); -1: none
+  int32_t relaxed;          // 1: no waits for rows of earlier batches (zc == zn, updated
+                            // in place: the asynchronous variant); 0: synchronous
 };
 
 // Prologue of an epoch (random partition, negatives, split-row lists, work
@@ -135,6 +142,9 @@ struct SetupArgs {
   uint16_t* bat;            // vertex -> batch index when nb <= 65536, else nullptr (a
                             // smaller copy of word for the prologue's random lookups)
   const int32_t* split_ids; // [nsplit] vertices of degree above chunk
+  int32_t* wcol;            // walk mode: [n][walk_k] walk neighbourhoods (else nullptr)
+  int32_t* wlen;            // walk mode: [n] their lengths (else nullptr)
+  int32_t walk_k;           // walk length k (0: neighbourhoods are the CSR rows)
   int32_t* pcol;            // [nnz] split rows' lists: early part, then late part
   int32_t* ecnt;            // vertex -> length of the early part of its list (split rows)
   int32_t* uoff;            // position -> offset of its whole unit among its batch's whole units
@@ -160,7 +170,7 @@ struct SetupArgs {
   int32_t identity;
   int32_t feistel_half;
   uint32_t feistel_mask;
-  const uint32_t* err;      // the context's error record: set = do nothing
+  const uint32_t* err;      // the context's error record: set = do nothing (k_walks: may be nullptr)
 };
 
 struct LossArgs {
@@ -213,6 +223,8 @@ hipError_t launch_negatives(int64_t n, int32_t b, int32_t s, uint64_t seed, uint
                             int32_t* negs, hipStream_t st);
 hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStream_t st);
 hipError_t launch_random_embedding(float* z, int64_t count, uint64_t seed, float scale, hipStream_t st);
+hipError_t launch_walks(const int64_t* rowptr, const int32_t* colidx, int64_t n, int32_t k, uint64_t seed,
+                        uint32_t epoch, int32_t* list, int32_t* len, hipStream_t st);
 // Completion record of a server job: the post-mortem if the job failed (see
 // kErrWords), then the job's device error record into host-visible memory
 // rec[1 .. kErrWords] and `seq` into rec[0] (written last).

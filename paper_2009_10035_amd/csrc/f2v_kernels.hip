@@ -26,6 +26,11 @@ __device__ int64_t block_inclusive_scan(int64_t v, int64_t* lds) {
   return r;
 }
 
+// Length of vertex u's list this epoch: its walk (walk mode) or its CSR row.
+__device__ __forceinline__ int64_t list_len(const SetupArgs& A, int32_t u) {
+  return A.wlen ? static_cast<int64_t>(A.wlen[u]) : A.rowptr[u + 1] - A.rowptr[u];
+}
+
 // Units of a row of degree deg: one, or ceil(deg / chunk) for split rows.
 __device__ __forceinline__ int32_t units_of(int64_t deg, int32_t chunk) {
   return deg <= chunk ? 1 : static_cast<int32_t>((deg + chunk - 1) / chunk);
@@ -85,6 +90,37 @@ __global__ void k_setup_positions(SetupArgs A) {
     const uint32_t k = static_cast<uint32_t>(q / A.s), j = static_cast<uint32_t>(q % A.s);
     const uint4 r = philox(A.epoch, k, j, kTagNeg, A.seed);
     A.negs[q] = uniform_index(r.x, r.y, A.n);
+  }
+}
+
+// K0 (walk mode): the random-walk neighbourhood of every vertex for this
+// epoch (Algorithm 3): from u, each step moves to a uniformly chosen
+// neighbour of the current vertex (step i draws Philox(e, u, i, kTagWalk)
+// and takes the neighbour at that uniform index of the current row), and a
+// vertex not yet in the list joins it, until the list holds k vertices, the
+// walk has taken 4k steps (fewer than k vertices may be reachable) or it
+// reaches a vertex without neighbours.  One thread per vertex; the list is
+// built in place in the output (a thread reads back only its own stores).
+__global__ void k_walks(SetupArgs A) {
+  if (A.err && *A.err != 0u) return;  // an earlier epoch failed
+  const int32_t k = A.walk_k;
+  for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < A.n;
+       u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int32_t* list = A.wcol + u * k;
+    int32_t len = 0, steps = 0;
+    int64_t w = u;
+    while (len < k && steps < 4 * k) {
+      const int64_t r0 = A.rowptr[w], deg = A.rowptr[w + 1] - r0;
+      if (deg == 0) break;
+      const uint4 x = philox(A.epoch, static_cast<uint32_t>(u), static_cast<uint32_t>(steps), kTagWalk, A.seed);
+      const int32_t next = A.colidx[r0 + uniform_index(x.x, x.y, deg)];
+      ++steps;
+      bool seen = false;
+      for (int32_t j = 0; j < len && !seen; ++j) seen = list[j] == next;
+      if (!seen) list[len++] = next;
+      w = next;
+    }
+    A.wlen[u] = len;
   }
 }
 
@@ -245,13 +281,12 @@ __global__ void k_sort_late(SetupArgs A) {
 // Work units of the row at a position: whole units in the low 32 bits, late
 // units in the high 32 bits (one of the two is 1, the other 0).
 __device__ __forceinline__ int64_t whole_late(const SetupArgs& A, int32_t u) {
-  const int64_t deg = A.rowptr[u + 1] - A.rowptr[u];
-  return deg <= A.chunk ? 1 : (int64_t{1} << 32);
+  return list_len(A, u) <= A.chunk ? 1 : (int64_t{1} << 32);
 }
 
 // Early units of the row of vertex u (split rows only).
 __device__ __forceinline__ int64_t early_units(const SetupArgs& A, int32_t u) {
-  const int64_t deg = A.rowptr[u + 1] - A.rowptr[u];
+  const int64_t deg = list_len(A, u);
   if (deg <= A.chunk) return 0;
   return (static_cast<int64_t>(A.ecnt[u]) + A.chunk - 1) / A.chunk;
 }
@@ -383,16 +418,17 @@ __global__ void k_tickets(SetupArgs A) {
     if (i < A.n) {
       const int32_t k = static_cast<int32_t>(i / A.b);
       const int32_t u = A.perm[i];
-      const int64_t r0 = A.rowptr[u], deg = A.rowptr[u + 1] - r0;
+      const int64_t r0 = A.rowptr[u], deg = list_len(A, u);
       Unit w;
       w.u = u;
       w.k = k;
       if (deg <= A.chunk) {
-        w.beg = r0;
+        // (walk lists are never longer than chunk, so they are whole units)
+        w.beg = A.wlen ? static_cast<int64_t>(u) * A.walk_k : r0;
         w.c = 0;
         w.nch = 0;
         w.len = static_cast<int32_t>(deg);
-        w.kind = kUnitWhole;
+        w.kind = A.wlen ? (kUnitWhole | kUnitWalk) : kUnitWhole;
         A.units[static_cast<int64_t>(A.bstart[k]) + A.uoff[i]] = w;
       } else {
         const int32_t early = A.ecnt[u];
@@ -646,6 +682,7 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
   const int64_t walkers = walk_threads(a.n);
   hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(walkers > nneg ? walkers : nneg, 256)), dim3(256), 0, st, a);
+  if (a.walk_k > 0) hipLaunchKernelGGL(k_walks, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a);
   if (a.nsplit > 0) {
     hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 16, 256)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * (64 / kSortRowsPerWave), 256)), dim3(256), 0, st,
@@ -739,6 +776,22 @@ hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const 
 
 hipError_t launch_postmortem(const uint32_t* word, int64_t n, uint32_t* err, hipStream_t st) {
   hipLaunchKernelGGL(k_postmortem, dim3(1), dim3(256), 0, st, word, n, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_walks(const int64_t* rowptr, const int32_t* colidx, int64_t n, int32_t k, uint64_t seed,
+                        uint32_t epoch, int32_t* list, int32_t* len, hipStream_t st) {
+  SetupArgs a{};
+  a.rowptr = rowptr;
+  a.colidx = colidx;
+  a.n = n;
+  a.walk_k = k;
+  a.seed = seed;
+  a.epoch = epoch;
+  a.wcol = list;
+  a.wlen = len;
+  a.err = nullptr;
+  hipLaunchKernelGGL(k_walks, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -61,14 +61,10 @@ struct WaveCounters {
 };
 
 // Atomic read of a word (a read-modify-write): performed where the word
-// lives, so it cannot return a stale cached copy.  The waits below poll with
-// device-scope loads and, on every 64th round, with an atomic read made by the
-// first lane of each group (every lane of a group waits for the same words).
-// When the atomic read finds the bit set and a plain device-scope load issued
-// after it still does not, the stale load is counted in the health record.
-// (A compare-and-swap whose expected value no vertex word or flag ever holds:
-// it fails and returns the current value.  An idempotent or-with-0 would do
-// the same, but the compiler folds that into a plain load.)
+// lives, so it cannot return a stale cached copy.  (A compare-and-swap whose
+// expected value no vertex word or flag ever holds: it fails and returns the
+// current value.  An idempotent or-with-0 would do the same, but the compiler
+// folds that into a plain load.)
 constexpr uint32_t kNeverAWord = 0x7fffffffu;  // batch index 2^31 - 1 > any batch, bit 31 clear
 __device__ __forceinline__ uint32_t atomic_read_u32(const uint32_t* p) {
   uint32_t expected = kNeverAWord;
@@ -77,19 +73,17 @@ __device__ __forceinline__ uint32_t atomic_read_u32(const uint32_t* p) {
   return expected;
 }
 
-// Bit `bit` of *p (p may be null: the lane polls nothing) by the group's
-// atomic read; every lane of a group gets the leader's answer.  All 64 lanes
-// must be active.
-template <int G>
-__device__ __forceinline__ bool atomic_poll(const EpochArgs& A, const uint32_t* p, uint32_t bit) {
-  const int lane = threadIdx.x & 63;
-  const bool leader = (lane % G) == 0;
-  uint32_t r = 0;
-  if (leader && p) r = atomic_read_u32(p);
-  if constexpr (G > 1) r = __shfl(r, lane - lane % G, 64);
-  const bool set = (r & bit) != 0u;
-  if (leader && p && set && (ld_coherent_u32(p) & bit) == 0u) atomicAdd(A.health + kHealthStale, 1u);
-  return set;
+// The waits poll with device-scope loads.  A wait that has polled 4096
+// times (far longer than any wait measured) also re-reads the word it waits
+// for atomically, at doubling poll counts: if that read finds the bit set, the
+// plain loads were stale, which is counted in the health record, and the wait
+// ends.  This stays out of the polling loop proper, which every unit runs.
+__device__ __forceinline__ bool long_wait_recheck(const EpochArgs& A, const uint32_t* p, uint32_t bit,
+                                                  uint32_t polls) {
+  if (polls < 4096u || (polls & (polls - 1u)) != 0u) return false;
+  if ((atomic_read_u32(p) & bit) == 0u) return false;
+  atomicAdd(A.health + kHealthStale, 1u);
+  return true;
 }
 
 // A wait that reached its bound: record the first give-up (what it waited for
@@ -111,8 +105,8 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
 // Bounded by a count of polls (A.max_polls, so a suspended wave cannot trip
 // it), or until another wave has reported a timeout; then it records the
-// give-up and returns.  All 64 lanes must be active.
-template <int G, int U>
+// give-up and returns.
+template <int U>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
   bool any = false;
@@ -123,47 +117,37 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
+    // each lane polls only its first pending entry, and the next one only if
+    // that one is published: few loads per round while many waves wait
     any = false;
-    if ((polls & 63u) != 63u) {
-      // each lane polls its first pending entry, and the next one only if
-      // that one is published: few loads per round while many waves wait
-      bool polled = false;
+    bool polled = false;
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (pend[q] && !polled) {
-          pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
-          polled = pend[q];
-        }
-        any |= pend[q];
+    for (int q = 0; q < U; ++q) {
+      if (pend[q] && !polled) {
+        pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+        polled = pend[q];
       }
-    } else {
-      int32_t v = -1;
-#pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (pend[q] && v < 0) v = vid[q];
-      const bool set = atomic_poll<G>(A, v >= 0 ? A.word + v : nullptr, kPublished);
-      bool done = false;
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (pend[q] && !done) {
-          done = true;
-          pend[q] = !set;
-        }
-        any |= pend[q];
-      }
+      any |= pend[q];
     }
     if (!__any(any)) break;
     ++polls;
     if ((polls & 63u) == 0) {
-      if (polls >= A.max_polls) {
-        int32_t v = -1;
+      if (ld_coherent_u32(A.err) != 0) break;
+      int32_t v = -1;
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (pend[q] && v < 0) v = vid[q];
+      if (v >= 0 && long_wait_recheck(A, A.word + v, kPublished, polls)) {
+        // only this entry is known published now; the loop polls the rest
 #pragma unroll
         for (int q = 0; q < U; ++q)
-          if (pend[q] && v < 0) v = vid[q];
+          if (vid[q] == v) pend[q] = false;
+        continue;
+      }
+      if (polls >= A.max_polls) {
         if (v >= 0) give_up(A, static_cast<uint32_t>(v) + 1u, A.word + v);
         break;
       }
-      if (ld_coherent_u32(A.err) != 0) break;
     }
     poll_backoff(polls);
   }
@@ -238,6 +222,15 @@ struct TreeLoads {
   static constexpr int value = 4;
 };
 
+// Force model whose coefficient a kernel instance evaluates: the instance's
+// family (kSigmoid: dot products; kStudentT: squared distances) fixes the
+// arithmetic on the rows, and inside the distance family the runtime model
+// (Student-t or a Table 2 model) picks the per-row coefficient.
+template <int kForce>
+__device__ __forceinline__ int32_t coef_force(const EpochArgs& A) {
+  return kForce == kSigmoid ? static_cast<int32_t>(kSigmoid) : A.force;
+}
+
 // Force coefficients of a batch of U entries from their per-lane partial dot
 // products (or squared distances); every lane of a group gets all U.
 template <int G, int kForce, int U>
@@ -255,7 +248,8 @@ __device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq
 #pragma unroll
       for (int q = 0; q < 8; ++q) dh[q] = dq[8 * h + q];
       const float dl = group_sum8_scatter<G>(dh);
-      const float cl = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+      const float cl = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(coef_force<kForce>(A), dl, A.eps)
+                                                         : attract_coef(coef_force<kForce>(A), dl);
       cq[8 * h + 0] = row_broadcast<0>(cl); cq[8 * h + 1] = row_broadcast<1>(cl);
       cq[8 * h + 2] = row_broadcast<2>(cl); cq[8 * h + 3] = row_broadcast<3>(cl);
       cq[8 * h + 4] = row_broadcast<4>(cl); cq[8 * h + 5] = row_broadcast<5>(cl);
@@ -269,7 +263,8 @@ __device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq
     for (int q = 0; q < U; ++q) repmask |= rep[q] ? (1u << q) : 0u;
     const float dl = group_sum8_scatter<G>(dq);
     const int row = static_cast<int>(threadIdx.x & 7);
-    const float cl = ((repmask >> row) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+    const float cl = ((repmask >> row) & 1u) ? repulse_coef(coef_force<kForce>(A), dl, A.eps)
+                                             : attract_coef(coef_force<kForce>(A), dl);
     cq[0] = row_broadcast<0>(cl); cq[1] = row_broadcast<1>(cl);
     cq[2] = row_broadcast<2>(cl); cq[3] = row_broadcast<3>(cl);
     cq[4] = row_broadcast<4>(cl); cq[5] = row_broadcast<5>(cl);
@@ -278,7 +273,7 @@ __device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const float t = group_sum<G>(dq[q]);
-      cq[q] = rep[q] ? repulse_coef(kForce, t, A.eps) : attract_coef(kForce, t);
+      cq[q] = rep[q] ? repulse_coef(coef_force<kForce>(A), t, A.eps) : attract_coef(coef_force<kForce>(A), t);
     }
   }
 }
@@ -305,7 +300,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait) wait_published<G, U>(A, vid, pend, wc);
+  if (kNext && wait) wait_published<U>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -344,7 +339,8 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
         dh[q] = pair_partial<R, V>(kForce, a, t);
       }
       const float dl = group_sum8_scatter<G>(dh);
-      cl[h] = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(kForce, dl, A.eps) : attract_coef(kForce, dl);
+      cl[h] = ((repmask >> (8 * h + row)) & 1u) ? repulse_coef(coef_force<kForce>(A), dl, A.eps)
+                                                : attract_coef(coef_force<kForce>(A), dl);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -498,9 +494,7 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
 }
 
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
-// the early sum of split row `u`.  Bounded like wait_published.  All 64 lanes
-// must be active.
-template <int G>
+// the early sum of split row `u`.  Bounded like wait_published.
 __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
@@ -508,20 +502,19 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
   uint32_t polls = 0;
 #pragma clang loop unroll(disable)
   while (true) {
-    if ((polls & 63u) != 63u) {
-      if (pend) pend = ld_coherent_u32(flag) == 0u;
-    } else {
-      const bool set = atomic_poll<G>(A, pend ? flag : nullptr, ~0u);
-      if (pend) pend = !set;
-    }
+    if (pend) pend = ld_coherent_u32(flag) == 0u;
     if (!__any(pend)) break;
     ++polls;
     if ((polls & 63u) == 0) {
+      if (ld_coherent_u32(A.err) != 0) break;
+      if (pend && long_wait_recheck(A, flag, ~0u, polls)) {
+        pend = false;
+        continue;
+      }
       if (polls >= A.max_polls) {
         if (pend) give_up(A, (static_cast<uint32_t>(u) + 1u) | kErrFlagWait, flag);
         break;
       }
-      if (ld_coherent_u32(A.err) != 0) break;
     }
     poll_backoff(polls);
   }
@@ -590,7 +583,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag<G>(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
+    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
@@ -604,7 +597,8 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   // attraction over the unit's neighbours, then (whole and late units)
   // repulsion from the batch's shared negatives: Algorithm 2's two loops
   const int32_t nneg = (active && !early) ? A.s : 0;
-  const int32_t* list = ((w.kind & kUnitReordered) ? A.pcol : A.colidx) + (active ? w.beg : 0);
+  const int32_t* list = ((w.kind & kUnitWalk) ? A.wcol : (w.kind & kUnitReordered) ? A.pcol : A.colidx) +
+                        (active ? w.beg : 0);
   const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
   if (A.force == kSigmoid)
     accumulate_unit<G, V, R, BF16, FULL, kSigmoid>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
@@ -784,7 +778,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
   } else {
     gbeg = 0;
     gend = *A.ngroups;
-    wait = true;
+    wait = A.relaxed == 0;
   }
   __shared__ WaveCounters wc_lds[4];
   WaveCounters& wc = wc_lds[threadIdx.x >> 6];

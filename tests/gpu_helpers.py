@@ -23,7 +23,8 @@ def lib_params(g, p: dict, **over):
         precision=q.get("precision", "fp32"), lr0=q["lr0"], lr_schedule=q.get("lr_schedule", "const"),
         eps=q.get("eps", 1e-3), total_epochs=q.get("total_epochs", 1),
         perm_mode=q.get("perm_mode", "random"), schedule=q.get("schedule", "dataflow"),
-        chunk=q.get("chunk", 0), seed=q["seed"], late_window=q.get("late_window"), fan_in=q.get("fan_in"))
+        chunk=q.get("chunk", 0), seed=q["seed"], late_window=q.get("late_window"), fan_in=q.get("fan_in"),
+        walk_length=q.get("walk_length", 0))
 
 
 def oracle_params(p: dict, **over) -> oracle.OracleParams:
@@ -33,7 +34,7 @@ def oracle_params(p: dict, **over) -> oracle.OracleParams:
                                eps=q.get("eps", 1e-3), lr0=q["lr0"],
                                lr_schedule=q.get("lr_schedule", "const"),
                                total_epochs=q.get("total_epochs", 1), seed=q["seed"],
-                               perm_mode=q.get("perm_mode", "random"))
+                               perm_mode=q.get("perm_mode", "random"), walk_length=q.get("walk_length", 0))
 
 
 def gpu_run(g, Z0, p: dict, epochs: int, first: int = 0, snapshots: bool = True, **over):
@@ -61,15 +62,16 @@ def rel_fro(a, b) -> float:
 
 
 def row_rel(a, b) -> float:
-    """Largest per-row relative error max_u |a_u - b_u| / |b_u| (Euclidean
-    norms), with row norms floored at 1% of the RMS row norm so that a row
-    near the origin does not divide by ~0.  A dropped or doubled term in one
-    row shows here even when it is invisible in the Frobenius norm of a
-    million-row matrix."""
+    """Largest per-row relative error max_u |a_u - b_u| / max(|b_u|, r)
+    (Euclidean norms), r the RMS row norm: the row's own scale, or the
+    typical one for a row near the origin, where FP32 rounding of the step's
+    terms is absolute rather than relative to the row.  A dropped or doubled
+    term in one row shows here (at ~1e-2) even when it is invisible in the
+    Frobenius norm of a million-row matrix."""
     a = np.asarray(a, dtype=np.float64).reshape(len(a), -1)
     b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
     nb = np.linalg.norm(b, axis=1)
-    floor = 1e-2 * np.sqrt(np.mean(nb ** 2)) if nb.size else 1.0
+    floor = np.sqrt(np.mean(nb ** 2)) if nb.size else 1.0
     return float(np.max(np.linalg.norm(a - b, axis=1) / np.maximum(nb, max(floor, 1e-30)))) if nb.size else 0.0
 
 
@@ -79,3 +81,28 @@ def assert_parity(got, ref, fro_tol: float, row_tol: float, what=""):
     assert f <= fro_tol and r <= row_tol, f"{what}: relative Frobenius {f:.3e} (bound {fro_tol:g}), " \
                                           f"row-wise max {r:.3e} (bound {row_tol:g})"
     return f, r
+
+
+def bf16_bits(x):
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().astype(np.int32)
+
+
+def bf16_compare(got, ref):
+    """Compare bf16 images of two master arrays: the share of bit-identical
+    images, and the largest difference in bf16 ulps among elements whose
+    masters differ by more than 1e-6 of the RMS element (near zero the
+    images may even differ in sign while the values agree to FP32 rounding
+    of the step, which is absolute there).  Ulps are counted on the ordered
+    line of bf16 values, so a sign change near zero is not a huge bit gap."""
+    a, b = bf16_bits(got), bf16_bits(ref)
+    same = float((a == b).mean()) if a.size else 1.0
+
+    def ordered(x):
+        mag = x & 0x7FFF
+        return np.where(x & 0x8000, -mag, mag)
+
+    ulps = np.abs(ordered(a) - ordered(b))
+    rms = float(np.sqrt(np.mean(np.asarray(ref, dtype=np.float64) ** 2))) if a.size else 1.0
+    far = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64)) > 1e-6 * rms
+    return same, int(ulps[far].max()) if far.any() else 0

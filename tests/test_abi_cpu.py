@@ -78,10 +78,12 @@ def test_default_chunk_follows_graph_size():
     ("n", 0, "F2V_E_INVALID_ARG"), ("n", 2**29, "F2V_E_INVALID_ARG"), ("d", 0, "F2V_E_INVALID_ARG"),
     ("d", 1025, "F2V_E_INVALID_ARG"), ("d", 130, "F2V_E_UNSUPPORTED"), ("d", 65, "F2V_E_UNSUPPORTED"),
     ("batch", 0, "F2V_E_INVALID_ARG"), ("s", -1, "F2V_E_INVALID_ARG"), ("s", 65, "F2V_E_INVALID_ARG"),
-    ("force", 2, "F2V_E_INVALID_ARG"), ("precision", 3, "F2V_E_INVALID_ARG"), ("lr0", 0.0, "F2V_E_INVALID_ARG"),
+    ("force", 5, "F2V_E_INVALID_ARG"), ("force", -1, "F2V_E_INVALID_ARG"), ("precision", 3, "F2V_E_INVALID_ARG"),
+    ("lr0", 0.0, "F2V_E_INVALID_ARG"), ("walk_length", 65, "F2V_E_INVALID_ARG"), ("walk_length", -1, "F2V_E_INVALID_ARG"),
+    ("fan_in", 3, "F2V_E_INVALID_ARG"), ("fan_in", 65, "F2V_E_INVALID_ARG"), ("late_window", 2**20 + 1, "F2V_E_INVALID_ARG"),
     ("lr0", float("nan"), "F2V_E_INVALID_ARG"), ("eps", 1.0, "F2V_E_INVALID_ARG"),
     ("eps", -0.1, "F2V_E_INVALID_ARG"), ("perm_mode", 2, "F2V_E_INVALID_ARG"),
-    ("schedule", 3, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
+    ("schedule", 4, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
 ])
 def test_validation(field, value, status):
     p = good()
@@ -90,6 +92,21 @@ def test_validation(field, value, status):
         f2v.workspace_size(p)
     assert ei.value.name == status
     assert f2v.load().f2v_last_error(None)
+
+
+def test_step_size_of_an_epoch():
+    """eta_e of Algorithm 1: lr0 (constant) or lr0 (1 - e / E) (linear); an
+    epoch at or past E under the linear schedule (eta <= 0) is refused, and
+    f2v_epoch refuses it the same way."""
+    lib = f2v.load()
+    out = ctypes.c_float(0)
+    p = good()
+    assert lib.f2v_step_size(ctypes.byref(p), 7, ctypes.byref(out)) == 0 and out.value == pytest.approx(0.02)
+    p = f2v.make_params(100, 200, 8, lr0=0.5, lr_schedule="linear", total_epochs=4)
+    for e, want in ((0, 0.5), (1, 0.375), (3, 0.125)):
+        assert lib.f2v_step_size(ctypes.byref(p), e, ctypes.byref(out)) == 0 and out.value == pytest.approx(want)
+    for e in (4, 5, -1):
+        assert _binding.STATUS[lib.f2v_step_size(ctypes.byref(p), e, ctypes.byref(out))] == "F2V_E_INVALID_ARG"
 
 
 def test_linear_schedule_needs_epochs_and_bf16_needs_even_d():

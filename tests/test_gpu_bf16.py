@@ -13,7 +13,7 @@ import torch
 import graphgen as gg
 import oracle
 import paper_2009_10035_amd as f2v
-from gpu_helpers import device_graph, gpu_run, lib_params, oracle_params, rel_fro
+from gpu_helpers import bf16_compare, device_graph, gpu_run, lib_params, oracle_params, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -26,11 +26,6 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def bf16_bits(x):
-    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
-    return t.view(torch.int16).numpy().astype(np.int32)
-
-
 # ("student_t", 128, 10) is the precision workload's configuration: one row
 # per wave with sixteen packed bf16 rows in flight
 @pytest.mark.parametrize("force,d,s", [("student_t", 64, 5), ("sigmoid", 128, 5), ("student_t", 2, 5),
@@ -41,9 +36,7 @@ def test_bf16_matches_emulation_one_epoch(force, d, s):
     Z0 = gg.init_embedding(g.n, d, 3)
     got = gpu_run(g, Z0, p, 1)[0]
     ref = oracle.epoch(g, Z0, 0, oracle_params(p), emul=True)
-    a, b = bf16_bits(got), bf16_bits(ref)
-    same = (a == b).mean()
-    ulps = np.abs(a - b).max()
+    same, ulps = bf16_compare(got, ref)
     print(f"bf16 images identical: {same:.5f}, max ulp diff {ulps}, master rel err {rel_fro(got, ref):.2e}")
     assert same >= 0.999 and ulps <= 1
     assert rel_fro(got, ref) <= 1e-4

@@ -14,7 +14,7 @@ import torch
 
 import graphgen as gg
 import oracle
-from gpu_helpers import assert_parity, gpu_run, oracle_params, rel_fro
+from gpu_helpers import assert_parity, bf16_compare, gpu_run, oracle_params, rel_fro
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -23,11 +23,6 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-
-
-def bf16_bits(x):
-    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
-    return t.view(torch.int16).numpy().astype(np.int32)
 
 
 def one_epoch(name, epoch_idx=1, emul=False):
@@ -51,9 +46,7 @@ def test_fp32_one_epoch_full_size(name):
 
 def test_bf16_one_epoch_full_size_sbm4m():
     got, ref = one_epoch("sbm4m", emul=True)
-    a, b = bf16_bits(got), bf16_bits(ref)
-    same = float((a == b).mean())
-    ulps = int(np.abs(a - b).max())
+    same, ulps = bf16_compare(got, ref)
     err = rel_fro(got, ref)
     print(f"sbm4m bf16: images identical {same:.6f}, max ulp difference {ulps}, master rel err {err:.2e}")
     assert same >= 0.999 and ulps <= 1

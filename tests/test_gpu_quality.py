@@ -1,0 +1,47 @@
+"""Embeddings trained on the device are useful for Section 4.4's tasks: on a
+planted-partition graph (20 blocks) the trained embedding predicts links,
+its k-means clusters recover the blocks (modularity near the planted
+partition's) and its rows classify the vertices' blocks, far above the
+random start on every task.  Checked for the sigmoid and Student-t models
+(Section 3.1) and for random-walk neighbourhoods (Algorithm 3)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import paper_2009_10035_amd as f2v
+from paper_2009_10035_amd import quality
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("force,walk", [("student_t", 0), ("sigmoid", 0), ("sigmoid", 5)])
+def test_trained_embedding_beats_random_start(force, walk):
+    n, blocks = 20000, 20
+    g = gg.sbm(n, blocks, 16.0, 1.0, seed=4)
+    labels = gg.sbm_blocks(n, blocks, seed=4)
+    Z0 = gg.init_embedding(n, 32, 5)
+    z = torch.from_numpy(Z0).cuda()
+    tr = f2v.Trainer(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.colidx).cuda(), z,
+                     f2v.make_params(n, g.nnz, 32, force=force, seed=6, walk_length=walk))
+    for e in range(40):
+        tr.epoch(e)
+    tr.sync_embedding()
+    tr.check()
+    tr.close()
+    ks = range(10, 31, 5)
+    got = quality.scores(g, z.cpu().numpy(), labels, ks=ks)
+    base = quality.scores(g, Z0, labels, ks=ks)
+    print(force, walk, "trained", got)
+    print(force, walk, "random ", base)
+    assert base["link_prediction_accuracy"] < 0.6 and base["best_kmeans_modularity"] < 0.1
+    assert base["node_classification_f1_micro"] < 0.2
+    assert got["link_prediction_accuracy"] > 0.8
+    assert got["best_kmeans_modularity"] > 0.7 * got["planted_modularity"]
+    assert got["node_classification_f1_micro"] > 0.8
