@@ -52,6 +52,7 @@ constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
 
+
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, negs, wreal,
       ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, health, wcol, wlen,
@@ -318,12 +319,15 @@ const char* f2v_status_string(f2v_status st) {
 
 const char* f2v_last_error(const f2v_ctx* ctx) { return ctx ? ctx->err.c_str() : g_error.c_str(); }
 
-f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
-                    void* d_ws, size_t ws_bytes, void* stream, f2v_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// Checks of f2v_init's arguments (host only, before any HIP call).
+f2v_status check_init_args(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
+                           void* d_ws, size_t ws_bytes) {
   f2v_status st = validate(p, nullptr);
   if (st != F2V_OK) return st;
-  if (!out) return fail(nullptr, F2V_E_INVALID_ARG, "out is NULL");
-  *out = nullptr;
   if (!d_rowptr || !d_z || !d_ws || (p->nnz > 0 && !d_colidx))
     return fail(nullptr, F2V_E_INVALID_ARG, "NULL device pointer");
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
@@ -334,8 +338,16 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   if (ws_bytes < L.total)
     return fail(nullptr, F2V_E_OOM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
                                         std::to_string(L.total));
-  f2v_ctx* c = new (std::nothrow) f2v_ctx();
-  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "host allocation failed");
+  return F2V_OK;
+}
+
+// Set up context `c` (checked arguments) and run the init kernels: the CSR
+// check and the split-row bookkeeping, read back with one synchronisation.
+// with_events: create the HIP events that time epochs (the entry point that
+// allocates nothing runs without them).  On failure the caller releases c.
+f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx,
+                         float* d_z, void* d_ws, void* stream, bool with_events) {
+  const Layout L = layout_of(*p);
   c->p = *p;
   c->p.chunk = chunk_of(c->p);
   c->L = L;
@@ -345,7 +357,8 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   c->z_user = d_z;
   c->ws = static_cast<char*>(d_ws);
   c->var = f2v::find_variant(p->d, p->precision == F2V_BF16);
-  c->update_fn = p->d == c->var->g * c->var->v * c->var->r ? c->var->update_full : c->var->update;
+  const int fam = f2v::force_family(p->force);
+  c->update_fn = p->d == c->var->g * c->var->v * c->var->r ? c->var->update_full[fam] : c->var->update[fam];
   const bool bf16 = p->precision == F2V_BF16;
   c->zbuf[0] = d_z;
   c->zbuf[1] = bf16 ? nullptr : c->at<float>(L.zbuf1);
@@ -354,9 +367,6 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
 
   auto bail = [&](f2v_status s, const std::string& m) {
     g_error = m;
-    for (hipEvent_t& e : c->ev)
-      if (e) (void)hipEventDestroy(e);
-    delete c;
     return s;
   };
   hipError_t he;
@@ -407,8 +417,10 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
     if (blocks > c->update_grid) blocks = c->update_grid;
     c->dynamic_grid = static_cast<int>(blocks);
   }
-  for (hipEvent_t& e : c->ev)
-    if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+  c->record_events = with_events;
+  if (with_events)
+    for (hipEvent_t& e : c->ev)
+      if ((he = hipEventCreate(&e)) != hipSuccess) return bail(F2V_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
 
   // The CSR check and the split-row setup are issued together and read back
   // with one synchronisation (on a busy device every round trip waits for
@@ -449,6 +461,26 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   // walk mode: every list is at most walk_length <= chunk entries, nothing is split
   c->hub_total = p->walk_length > 0 ? 0 : hub_total;
   c->nsplit = p->walk_length > 0 ? 0 : nsplit;
+  return F2V_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
+                    void* d_ws, size_t ws_bytes, void* stream, f2v_ctx** out) {
+  if (!out) return fail(nullptr, F2V_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  f2v_status st = check_init_args(p, d_rowptr, d_colidx, d_z, d_ws, ws_bytes);
+  if (st != F2V_OK) return st;
+  f2v_ctx* c = new (std::nothrow) f2v_ctx();
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "host allocation failed");
+  st = setup_context(c, p, d_rowptr, d_colidx, d_z, d_ws, stream, true);
+  if (st != F2V_OK) {
+    f2v_destroy(c);
+    return st;
+  }
   *out = c;
   return F2V_OK;
 }

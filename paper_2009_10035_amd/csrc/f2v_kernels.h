@@ -186,14 +186,20 @@ struct LossArgs {
 };
 
 // Kernel variant of one embedding width: G lanes per row, V consecutive
-// elements per lane and load, R loads per lane to cover a row.
+// elements per lane and load, R loads per lane to cover a row.  One update
+// kernel per force family: [0] sigmoid, [1] Student-t, [2] the Table 2
+// models (see force_family).
 struct Variant {
   int g, v, r;
   bool bf16;
-  const void* update;       // __global__ void(EpochArgs), any d <= g * v * r
-  const void* update_full;  // the same for d = g * v * r (no lane past the row's end)
-  const void* loss;         // __global__ void(LossArgs)
+  const void* update[3];       // __global__ void(EpochArgs), any d <= g * v * r
+  const void* update_full[3];  // the same for d = g * v * r (no lane past the row's end)
+  const void* loss;            // __global__ void(LossArgs)
 };
+
+// Update-kernel family of a force model (f2v_force): 0 sigmoid, 1 Student-t,
+// 2 Fruchterman-Reingold, LinLog and ForceAtlas.
+inline int force_family(int32_t force) { return force <= 1 ? force : 2; }
 
 // Variant for (d, bf16), or nullptr if d is not supported.
 const Variant* find_variant(int d, bool bf16);

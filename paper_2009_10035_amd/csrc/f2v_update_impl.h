@@ -222,13 +222,16 @@ struct TreeLoads {
   static constexpr int value = 4;
 };
 
-// Force model whose coefficient a kernel instance evaluates: the instance's
-// family (kSigmoid: dot products; kStudentT: squared distances) fixes the
-// arithmetic on the rows, and inside the distance family the runtime model
-// (Student-t or a Table 2 model) picks the per-row coefficient.
+// Force family of a kernel instance (its kForce template argument): kSigmoid
+// (dot products), kStudentT (squared distances, Eq. 8-9 coefficients) or
+// kTable2 (squared distances, the coefficient of the runtime model: FR,
+// LinLog or ForceAtlas).  Each family is compiled into an update kernel of its
+// own, so that no instance carries another model's arithmetic.
+constexpr int kTable2 = 2;
 template <int kForce>
 __device__ __forceinline__ int32_t coef_force(const EpochArgs& A) {
-  return kForce == kSigmoid ? static_cast<int32_t>(kSigmoid) : A.force;
+  if constexpr (kForce == kTable2) return A.force;
+  else return kForce;
 }
 
 // Force coefficients of a batch of U entries from their per-lane partial dot
@@ -540,7 +543,7 @@ __device__ __forceinline__ void store_partial(float* row, int d, int l, const fl
 // One work unit (see the unit kinds): accumulate its list, then either take
 // the step of Eq. 10 and publish the row (whole and late units) or add the
 // partial sum into the row's combining tree (early units).
-template <int G, int V, int R, bool BF16, bool FULL>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM>
 __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
                                              bool wait, uint32_t* order, WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
@@ -600,12 +603,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const int32_t* list = ((w.kind & kUnitWalk) ? A.wcol : (w.kind & kUnitReordered) ? A.pcol : A.colidx) +
                         (active ? w.beg : 0);
   const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
-  if (A.force == kSigmoid)
-    accumulate_unit<G, V, R, BF16, FULL, kSigmoid>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
-                                             acc, wc);
-  else
-    accumulate_unit<G, V, R, BF16, FULL, kStudentT>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a,
-                                              acc, wc);
+  accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a, acc, wc);
 
   if (A.wave_stats && __any(late)) wc.wait_late += wc.wait - wait_before;
 
@@ -752,7 +750,7 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
   }
 }
 
-template <int G, int V, int R, bool BF16, bool FULL>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM>
 // Packed bf16 rows with one row per wave: sixteen rows in flight need more
 // registers than six waves per SIMD leave; the compiler is held to that
 // occupancy (a few values of the unit loop go to scratch).
@@ -821,7 +819,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
     nxt.u = -1;
     if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
     const int gnn = __builtin_amdgcn_readfirstlane(gn < gend ? following(gn) : gend);
-    process_unit<G, V, R, BF16, FULL>(A, cur, l, slot, wait, order, wc);
+    process_unit<G, V, R, BF16, FULL, FAM>(A, cur, l, slot, wait, order, wc);
     cur = nxt;
     g = gn;
     gn = gnn;
@@ -870,6 +868,84 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
     double la = 0.0, lr = 0.0;
     const int64_t r0 = active ? A.rowptr[u] : 0;
     const int64_t len = active ? A.rowptr[u + 1] - r0 : 0;
+    if constexpr (G >= 16) {
+      // eight rows in flight, their eight dot products (or squared distances)
+      // reduced at once; after the reduction lane l of the group holds entry
+      // l % 8's, and the group's first eight lanes each add one entry's term
+      double ta = 0.0, tr = 0.0;
+      const int seg = l & 7;
+      const bool keeper = l < 8;
+      for (int64_t off = 0; __any(active && off < len); off += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          v[q] = (active && off + q < len) ? A.colidx[r0 + off + q] : -1;
+          if constexpr (G == 64) v[q] = __builtin_amdgcn_readfirstlane(v[q]);
+        }
+        float y[8][R][V], dq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (v[q] >= 0) {
+            load_row<G, V, R, BF16>(z, v[q], A.d, l, false, y[q]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
+        const float dl = group_sum8_scatter<G>(dq);
+        int32_t mine = -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mine = seg == q ? v[q] : mine;
+        if (keeper && mine >= 0) ta += static_cast<double>(attract_loss(A.force, dl));
+      }
+      for (int32_t j0 = 0; j0 < A.s; j0 += 8) {
+        int32_t w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          w[q] = -1;
+          if (active && j0 + q < A.s) {
+            const uint4 x = philox(static_cast<uint32_t>(u), static_cast<uint32_t>(static_cast<uint64_t>(u) >> 32),
+                                   static_cast<uint32_t>(j0 + q), kTagEval, A.seed);
+            w[q] = uniform_index(x.x, x.y, A.n);
+          }
+        }
+        float y[8][R][V], dq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (w[q] >= 0) {
+            load_row<G, V, R, BF16>(z, w[q], A.d, l, false, y[q]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
+        const float dl = group_sum8_scatter<G>(dq);
+        int32_t mine = -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mine = seg == q ? w[q] : mine;
+        if (keeper && mine >= 0) tr += static_cast<double>(repulse_loss(A.force, dl, A.eps));
+      }
+      // the eight keepers' sums, added in a fixed pattern (every keeper ends
+      // with the same bits); lane 0 of the group stores them
+#pragma unroll
+      for (int m = 4; m >= 1; m >>= 1) {
+        ta += __shfl_xor(ta, m, 64);
+        tr += __shfl_xor(tr, m, 64);
+      }
+      if (active && l == 0) {
+        A.part[2 * u] = ta;
+        A.part[2 * u + 1] = tr;
+      }
+      continue;
+    }
     for (int64_t off = 0;; off += kStep) {
       const bool more = active && off < len;
       if (!__any(more)) break;

@@ -4,8 +4,13 @@
 namespace f2v {
 
 #define F2V_VARIANT(G, V, R, B) \
-  Variant{G, V, R, B, reinterpret_cast<const void*>(&k_update<G, V, R, B, false>), \
-          reinterpret_cast<const void*>(&k_update<G, V, R, B, true>), \
+  Variant{G, V, R, B, \
+          {reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 0>), \
+           reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 1>), \
+           reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 2>)}, \
+          {reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 0>), \
+           reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 1>), \
+           reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 2>)}, \
           reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
 
 extern const Variant kVariants_f32_v4[] = {

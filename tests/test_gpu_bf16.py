@@ -36,9 +36,9 @@ def test_bf16_matches_emulation_one_epoch(force, d, s):
     Z0 = gg.init_embedding(g.n, d, 3)
     got = gpu_run(g, Z0, p, 1)[0]
     ref = oracle.epoch(g, Z0, 0, oracle_params(p), emul=True)
-    same, ulps = bf16_compare(got, ref)
-    print(f"bf16 images identical: {same:.5f}, max ulp diff {ulps}, master rel err {rel_fro(got, ref):.2e}")
-    assert same >= 0.999 and ulps <= 1
+    same, bad = bf16_compare(got, ref)
+    print(f"bf16 images identical: {same:.5f}, beyond one ulp at the RMS scale: {bad}, master rel err {rel_fro(got, ref):.2e}")
+    assert same >= 0.999 and bad == 0
     assert rel_fro(got, ref) <= 1e-4
 
 

@@ -3,7 +3,10 @@ planted-partition graph (20 blocks) the trained embedding predicts links,
 its k-means clusters recover the blocks (modularity near the planted
 partition's) and its rows classify the vertices' blocks, far above the
 random start on every task.  Checked for the sigmoid and Student-t models
-(Section 3.1) and for random-walk neighbourhoods (Algorithm 3)."""
+(Section 3.1) and for random-walk neighbourhoods (Algorithm 3), after 200
+epochs (the sigmoid model needs about 100 here; the paper runs 1200).  At
+40 epochs the device's scores agree with the FP64 oracle's to three digits
+(0.935 link prediction, 0.588 modularity, 0.765 F1 for the sigmoid).""" 
 import numpy as np
 import pytest
 import torch
@@ -30,7 +33,7 @@ def test_trained_embedding_beats_random_start(force, walk):
     z = torch.from_numpy(Z0).cuda()
     tr = f2v.Trainer(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.colidx).cuda(), z,
                      f2v.make_params(n, g.nnz, 32, force=force, seed=6, walk_length=walk))
-    for e in range(40):
+    for e in range(200):
         tr.epoch(e)
     tr.sync_embedding()
     tr.check()
