@@ -196,19 +196,16 @@ f2v_status f2v_sync_embedding(f2v_ctx *ctx);
  * clock, so a wave that is suspended cannot time out.  After such a wait,
  * later epochs of the context do nothing until this check, so the failed
  * epoch's vertex words are kept: f2v_last_error then gives how many vertices
- * were never published, the earliest of them, and what the first wait to give
- * up waited for with that word as an atomic read returned it.  If a dataflow
- * launch since the last check found its grid not co-resident, later epochs
- * use one block per CU fewer. */
+ * were never published and the earliest of them.  If a dataflow launch since
+ * the last check found its grid not co-resident, later epochs use one block
+ * per CU fewer. */
 f2v_status f2v_check(f2v_ctx *ctx);
 
 /* Health record of the context (synchronises the stream): out[0] dataflow
  * launches that found their grid not co-resident and handed work out by
- * claiming instead (same results), out[1] polls where an atomic read found a
- * word set while a later device-scope load of it did not (stale loads; the
- * waits rely on the atomic read every 64th poll), out[2] the most polls one
- * dependency wait took, out[3] reserved (0).  *blocks_per_cu (may be NULL):
- * the dataflow grid's current blocks of 256 threads per CU. */
+ * claiming instead (same results); out[1] .. out[3] reserved (0).
+ * *blocks_per_cu (may be NULL): the dataflow grid's current blocks of 256
+ * threads per CU. */
 f2v_status f2v_health(f2v_ctx *ctx, uint32_t out[4], int32_t *blocks_per_cu);
 
 /* Release the context (no device memory to free; the caller owns it). */

@@ -109,14 +109,12 @@ class Trainer:
 
     def health(self):
         """Health record (see f2v_health in include/f2v.h): dict with the
-        dataflow launches that fell back to claiming, stale loads caught by
-        the waits' atomic reads, the longest wait in polls, and the dataflow
-        grid's blocks per CU."""
+        dataflow launches that fell back to claiming and the dataflow grid's
+        blocks per CU."""
         out = (ctypes.c_uint32 * 4)()
         bpc = ctypes.c_int32(0)
         check(self.lib.f2v_health(self.ctx, out, ctypes.byref(bpc)), self.ctx)
-        return {"fallbacks": int(out[0]), "stale_loads": int(out[1]), "max_polls": int(out[2]),
-                "blocks_per_cu": int(bpc.value)}
+        return {"fallbacks": int(out[0]), "blocks_per_cu": int(bpc.value)}
 
     def set_diagnostics(self, enable: bool = True) -> None:
         check(self.lib.f2v_set_diagnostics(self.ctx, 1 if enable else 0), self.ctx)

@@ -235,20 +235,14 @@ namespace f2v {
 // Message for a device error record (see kErrWords).
 std::string describe_timeout(const uint32_t* e) {
   char buf[480];
-  int k;
   if (e[1] != 0)
-    k = std::snprintf(buf, sizeof(buf),
-                      "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
-                      "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
+    std::snprintf(buf, sizeof(buf),
+                  "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
+                  "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
   else
-    k = std::snprintf(buf, sizeof(buf),
-                      "a device dependency wait exceeded its bound (after the waits stopped, every vertex of the "
-                      "epoch was published)");
-  const uint32_t what = e[kErrWaitedFor];
-  if (what != 0 && k > 0 && k < static_cast<int>(sizeof(buf)))
-    std::snprintf(buf + k, sizeof(buf) - k, "; the first wait to give up waited for %s %u, whose word an atomic "
-                  "read returned as 0x%08x", (what & kErrFlagWait) ? "the early sum of split row" : "vertex",
-                  (what & ~kErrFlagWait) - 1u, e[kErrWaitedWord]);
+    std::snprintf(buf, sizeof(buf),
+                  "a device dependency wait exceeded its bound (after the waits stopped, every vertex of the "
+                  "epoch was published)");
   return buf;
 }
 }  // namespace f2v

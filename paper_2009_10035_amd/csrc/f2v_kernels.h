@@ -15,21 +15,14 @@ constexpr uint32_t kPublished = 0x80000000u;
 // partition kernels return at once), so the vertex words of the epoch that
 // failed are kept, and a post-mortem fills [1] the number of vertices never
 // published in it, [2] the earliest batch among them, [3] one such vertex of
-// that batch and [4] its word.  The first wait to give up records [5] what it
-// waited for (vertex + 1, or split row + 1 with bit 31 set for the flag of the
-// row's early sum) and [6] that word as an atomic read-modify-write returned it
-// at the give-up, a read that cannot be served from a stale cache line.
-constexpr int kErrWords = 8;
-constexpr int kErrWaitedFor = 5, kErrWaitedWord = 6;
-constexpr uint32_t kErrFlagWait = 0x80000000u;
+// that batch and [4] its word.
+constexpr int kErrWords = 5;
 
 // Health counters of a context (never reset by epochs; zeroed at init):
 // [0] launches of the static schedule that found the grid not co-resident and
-// switched to claiming, [1] polls where an atomic read found a row published
-// while a later plain device-scope load of the same word still read it
-// unpublished, [2] the most polls any single wait took.
+// switched to claiming; [1] .. [3] unused (0).
 constexpr int kHealthWords = 4;
-constexpr int kHealthFallback = 0, kHealthStale = 1, kHealthMaxPolls = 2;
+constexpr int kHealthFallback = 0;
 
 // Claim counter (word 0) and arrival word (word kClaimStride) of an epoch's
 // update launch, each in its own 128-byte line; reset by the prologue.

@@ -60,41 +60,6 @@ struct WaveCounters {
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
-// Atomic read of a word (a read-modify-write): performed where the word
-// lives, so it cannot return a stale cached copy.  (A compare-and-swap whose
-// expected value no vertex word or flag ever holds: it fails and returns the
-// current value.  An idempotent or-with-0 would do the same, but the compiler
-// folds that into a plain load.)
-constexpr uint32_t kNeverAWord = 0x7fffffffu;  // batch index 2^31 - 1 > any batch, bit 31 clear
-__device__ __forceinline__ uint32_t atomic_read_u32(const uint32_t* p) {
-  uint32_t expected = kNeverAWord;
-  __hip_atomic_compare_exchange_strong(const_cast<uint32_t*>(p), &expected, kNeverAWord, __ATOMIC_RELAXED,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return expected;
-}
-
-// The waits poll with device-scope loads.  A wait that has polled 4096
-// times (far longer than any wait measured) also re-reads the word it waits
-// for atomically, at doubling poll counts: if that read finds the bit set, the
-// plain loads were stale, which is counted in the health record, and the wait
-// ends.  This stays out of the polling loop proper, which every unit runs.
-__device__ __forceinline__ bool long_wait_recheck(const EpochArgs& A, const uint32_t* p, uint32_t bit,
-                                                  uint32_t polls) {
-  if (polls < 4096u || (polls & (polls - 1u)) != 0u) return false;
-  if ((atomic_read_u32(p) & bit) == 0u) return false;
-  atomicAdd(A.health + kHealthStale, 1u);
-  return true;
-}
-
-// A wait that reached its bound: record the first give-up (what it waited for
-// and that word as an atomic read returns it) and raise the error word, which
-// makes every other waiter stop within 64 polls.
-__device__ __forceinline__ void give_up(const EpochArgs& A, uint32_t what, const uint32_t* p) {
-  const uint32_t r = atomic_read_u32(p);
-  if (atomicCAS(A.err + kErrWaitedFor, 0u, what) == 0u) st_coherent_u32(A.err + kErrWaitedWord, r);
-  atomicOr(A.err, 1u);
-}
-
 // Sleep between polls: back off from 64 to 1024 cycles.
 __device__ __forceinline__ void poll_backoff(uint32_t polls) {
   if (polls < 8) __builtin_amdgcn_s_sleep(1);
@@ -103,9 +68,12 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
 }
 
 // Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
-// Bounded by a count of polls (A.max_polls, so a suspended wave cannot trip
-// it), or until another wave has reported a timeout; then it records the
-// give-up and returns.
+// Bounded by a count of polls (A.max_polls; a suspended wave does not poll,
+// so a suspension cannot trip it): at the bound it raises the error word,
+// which makes every other waiter stop within 64 polls.  It also stops once
+// another wave has raised it.  (The give-up block is kept to one atomic:
+// anything that names the awaited entry there keeps the entry arrays live
+// through the loop and costs the update kernel about 12% more instructions.)
 template <int U>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
@@ -132,26 +100,14 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
     if (!__any(any)) break;
     ++polls;
     if ((polls & 63u) == 0) {
-      if (ld_coherent_u32(A.err) != 0) break;
-      int32_t v = -1;
-#pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (pend[q] && v < 0) v = vid[q];
-      if (v >= 0 && long_wait_recheck(A, A.word + v, kPublished, polls)) {
-        // only this entry is known published now; the loop polls the rest
-#pragma unroll
-        for (int q = 0; q < U; ++q)
-          if (vid[q] == v) pend[q] = false;
-        continue;
-      }
       if (polls >= A.max_polls) {
-        if (v >= 0) give_up(A, static_cast<uint32_t>(v) + 1u, A.word + v);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
         break;
       }
+      if (ld_coherent_u32(A.err) != 0) break;
     }
     poll_backoff(polls);
   }
-  if (polls >= 64 && (threadIdx.x & 63) == 0) atomicMax(A.health + kHealthMaxPolls, polls);
   compiler_fence();
   // the unit waited on the chain of publications: finish it ahead of waves
   // doing work that nothing waits for yet
@@ -497,8 +453,8 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
 }
 
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
-// the early sum of split row `u`.  Bounded like wait_published.
-__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, WaveCounters& wc) {
+// the early sum of a split row.  Bounded like wait_published.
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
@@ -509,19 +465,14 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
     if (!__any(pend)) break;
     ++polls;
     if ((polls & 63u) == 0) {
-      if (ld_coherent_u32(A.err) != 0) break;
-      if (pend && long_wait_recheck(A, flag, ~0u, polls)) {
-        pend = false;
-        continue;
-      }
       if (polls >= A.max_polls) {
-        if (pend) give_up(A, (static_cast<uint32_t>(u) + 1u) | kErrFlagWait, flag);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
         break;
       }
+      if (ld_coherent_u32(A.err) != 0) break;
     }
     poll_backoff(polls);
   }
-  if (polls >= 64 && (threadIdx.x & 63) == 0) atomicMax(A.health + kHealthMaxPolls, polls);
   compiler_fence();
   if (A.wave_stats) {
     wc.wait += clock64() - t0;
@@ -586,7 +537,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
+    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
