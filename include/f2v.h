@@ -208,6 +208,25 @@ f2v_status f2v_check(f2v_ctx *ctx);
  * threads per CU. */
 f2v_status f2v_health(f2v_ctx *ctx, uint32_t out[4], int32_t *blocks_per_cu);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): a whole run of the method
+ * -- the checks and setup of f2v_init, epochs first_epoch .. first_epoch +
+ * epochs - 1 as f2v_epoch runs them, f2v_sync_embedding and f2v_check --
+ * with its workspace in a static device array of the library instead of a
+ * caller's buffer.  The array holds 256 MiB (268435456 bytes) on every device
+ * the library runs on, from the first call on that device until the process
+ * ends; a job whose f2v_workspace_size is larger is refused with F2V_E_OOM
+ * before any device work.  The call allocates no device memory and creates no
+ * HIP events; it synchronises `stream` (at the CSR check and at the end).
+ * d_rowptr, d_colidx, d_z as f2v_init (d_z receives the result: the FP32
+ * embedding, or the FP32 master rows in the bf16 form).  Every call on a
+ * device shares that device's array, which keeps the last call's contents
+ * (each call initialises what it reads): calls that overlap on one device
+ * race and must not be issued.  Returns the first error (F2V_E_TIMEOUT with
+ * the message of f2v_check). */
+f2v_status f2v_train_static(const f2v_params *p, const int64_t *d_rowptr, const int32_t *d_colidx, float *d_z,
+                            int32_t first_epoch, int32_t epochs, void *stream);
+
 /* Release the context (no device memory to free; the caller owns it). */
 f2v_status f2v_destroy(f2v_ctx *ctx);
 

@@ -20,7 +20,7 @@ EXPORTS = (
     "f2v_vertex_trace", "f2v_footprint", "f2v_server_create", "f2v_server_submit",
     "f2v_server_flush", "f2v_server_poll", "f2v_server_query", "f2v_server_drain",
     "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding", "f2v_health",
-    "f2v_walks", "f2v_step_size",
+    "f2v_walks", "f2v_step_size", "f2v_train_static",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",

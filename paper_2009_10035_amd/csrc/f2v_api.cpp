@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -52,6 +53,16 @@ constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
 
+// Workspace of f2v_train_static, the entry point for callers that cannot
+// allocate: a file-scope device array, one per GPU the library runs on, held
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not the device memory: the device address comes from hipGetSymbolAddress,
+// once per device, and only that address is handed to kernels.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
 
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, negs, wreal,
@@ -461,6 +472,50 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
 }  // namespace
 
 extern "C" {
+
+f2v_status f2v_train_static(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
+                            int32_t first_epoch, int32_t epochs, void* stream) {
+  f2v_status st = validate(p, nullptr);
+  if (st != F2V_OK) return st;
+  if (first_epoch < 0 || epochs < 0) return fail(nullptr, F2V_E_INVALID_ARG, "first_epoch and epochs must be >= 0");
+  const size_t need = layout_of(*p).total;
+  if (need > kScratchBytes)
+    return fail(nullptr, F2V_E_OOM, "the job needs a workspace of " + std::to_string(need) +
+                                        " bytes; the static workspace holds " + std::to_string(kScratchBytes));
+  // the device address of this device's copy of the static workspace
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(nullptr, F2V_E_UNSUPPORTED, "device index above 63");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+      he = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+      if (he != hipSuccess) {
+        g_scratch_ptr[dev] = nullptr;
+        return fail(nullptr, F2V_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(he));
+      }
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  st = check_init_args(p, d_rowptr, d_colidx, d_z, ws, kScratchBytes);
+  if (st != F2V_OK) return st;
+  // the context lives on this stack frame; no HIP events (they would be
+  // allocations), no device memory beyond the static workspace
+  f2v_ctx c;
+  st = setup_context(&c, p, d_rowptr, d_colidx, d_z, ws, stream, false);
+  for (int32_t e = first_epoch; st == F2V_OK && e < first_epoch + epochs; ++e) {
+    st = f2v_epoch(&c, e);
+    if (st != F2V_OK) g_error = c.err;
+  }
+  if (st == F2V_OK) st = f2v_sync_embedding(&c);
+  if (st == F2V_OK) {
+    st = f2v_check(&c);
+    if (st != F2V_OK) g_error = c.err;
+  }
+  return st;
+}
 
 f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t* d_colidx, float* d_z,
                     void* d_ws, size_t ws_bytes, void* stream, f2v_ctx** out) {

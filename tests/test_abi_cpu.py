@@ -132,3 +132,18 @@ def test_init_rejects_bad_pointers_without_touching_the_device():
     assert _binding.STATUS[st] == "F2V_E_INVALID_ARG"   # misaligned workspace
     assert lib.f2v_epoch(None, 0) == 1 and lib.f2v_destroy(None) == 0
     assert lib.f2v_status_string(6) == b"device dependency wait timed out"
+
+
+def test_static_workspace_entry_refuses_oversize_jobs_on_the_host():
+    """f2v_train_static (callers that cannot allocate) refuses a job whose
+    workspace exceeds its static array before any HIP call, and checks its
+    arguments like f2v_init."""
+    lib = f2v.load()
+    lib.f2v_train_static.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    big = f2v.make_params(2_000_000, 40_000_000, 128)
+    st = lib.f2v_train_static(ctypes.cast(ctypes.pointer(big), ctypes.c_void_p), 256, 512, 1024, 0, 1, None)
+    assert _binding.STATUS[st] == "F2V_E_OOM"
+    assert b"static workspace holds 268435456" in lib.f2v_last_error(None)
+    p = good()
+    st = lib.f2v_train_static(ctypes.cast(ctypes.pointer(p), ctypes.c_void_p), 256, 512, 1024, -1, 1, None)
+    assert _binding.STATUS[st] == "F2V_E_INVALID_ARG"
