@@ -263,7 +263,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict", "dynamic"])
+    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "strict", "dynamic", "hogwild"])
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
                     help="override the workload's precision (to compare the two forms on one graph)")

@@ -192,7 +192,7 @@ f2v_status f2v_sync_embedding(f2v_ctx *ctx);
 
 /* Synchronise the stream and report a device-side error raised since the
  * last check (F2V_E_TIMEOUT for an exceeded dependency wait).  A wait is
- * bounded by a count of polls (2^22, more than a second of polling), not by a
+ * bounded by a count of polls (2^20, about half a second of polling), not by a
  * clock, so a wave that is suspended cannot time out.  After such a wait,
  * later epochs of the context do nothing until this check, so the failed
  * epoch's vertex words are kept: f2v_last_error then gives how many vertices
@@ -241,6 +241,22 @@ f2v_status f2v_partition(int64_t n, uint64_t seed, int32_t epoch, int32_t perm_m
                          int32_t *d_perm, void *stream);
 f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int32_t epoch,
                          int32_t *d_S, void *stream);
+
+/* Device self-test of the publication protocol that keeps the update's reads
+ * exact while batches overlap (the synchronous minibatch semantics of
+ * Algorithm 1 on a device whose XCDs have caches that are not coherent with
+ * each other).  `pairs` pairs of single-wave workgroups, writer and reader
+ * on different XCDs, run `rounds` rounds: the writer publishes a 512-byte
+ * row exactly as the update kernel publishes an updated row (device-scope
+ * row stores, wait for their completion, device-scope flag store), the
+ * reader polls the flag and reads the row as a dependent unit does, checks
+ * every word, and acknowledges.  1 <= pairs <= 1024, 1 <= rounds <= 2^24.
+ * d_ws: caller's device buffer, 256-byte aligned, of at least
+ * 512 * pairs + 4 * (2 * pairs + 3) bytes.  out (host): [0] words read
+ * stale, [1] polls that ran into the wait bound, [2] readers that completed
+ * every round (a sound device gives 0, 0, pairs).  Synchronises `stream`. */
+f2v_status f2v_selftest_publish(int32_t pairs, int32_t rounds, void *d_ws, size_t ws_bytes, uint32_t out[3],
+                                void *stream);
 
 /* Device copy of the random-walk neighbourhoods of epoch e (walk mode,
  * Algorithm 3; see walk_length): for every vertex u, d_len[u] <= k and its

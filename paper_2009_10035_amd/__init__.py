@@ -181,6 +181,17 @@ def walks(rowptr: torch.Tensor, colidx: torch.Tensor, k: int, seed: int, epoch: 
     return lst, ln
 
 
+def selftest_publish(pairs: int = 256, rounds: int = 10000, device="cuda") -> dict:
+    """Device self-test of the cross-XCD publication protocol (see
+    f2v_selftest_publish in include/f2v.h) on the current stream: words
+    read stale, polls that ran into the wait bound, readers that completed
+    (a sound device: 0, 0, pairs)."""
+    ws = torch.empty(512 * pairs + 4 * (2 * pairs + 3), dtype=torch.uint8, device=device)
+    out = (ctypes.c_uint32 * 3)()
+    check(load().f2v_selftest_publish(pairs, rounds, ws.data_ptr(), ws.numel(), out, _stream_handle(ws.device)))
+    return {"stale": int(out[0]), "timeouts": int(out[1]), "completed": int(out[2])}
+
+
 def negatives(n: int, batch: int, s: int, seed: int, epoch: int, device="cuda") -> torch.Tensor:
     """S[k, j] of every batch of the epoch on the device (int32 [nb, s])."""
     nb = (n + batch - 1) // batch

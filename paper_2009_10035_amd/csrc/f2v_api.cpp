@@ -1,13 +1,16 @@
 // Host side of the C ABI declared in include/f2v.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
-#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "../../include/f2v.h"
 #include "f2v_device.h"
@@ -39,12 +42,13 @@ constexpr int32_t kDefaultFanIn = 8;
 // in closed loop (300 jobs, 16 slots), against 77 at 8, 78 at 2 and 70 at 1.
 constexpr int64_t kDynamicLookahead = 4;
 // Bound on one dependency wait, in polls.  A poll is a load plus a sleep of
-// 64 to 1024 cycles, so 2^22 polls are more than a second of waiting, far
+// 64 to 1024 cycles, so 2^20 polls are about half a second of waiting, far
 // beyond any legitimate wait (a unit waits only for the few batches in flight
 // before its own; the longest epoch measured here is 15 ms).  A count of polls
 // rather than a clock: a wave that is suspended does not poll, so time spent
-// suspended cannot make a wait give up.
-constexpr uint32_t kMaxPolls = 1u << 22;
+// suspended cannot make a wait give up.  Not longer: while a stalled launch
+// runs, later kernels of streams that share its hardware queue wait for it.
+constexpr uint32_t kMaxPolls = 1u << 20;
 // Static schedule: how long the first waves of a launch wait for the rest of
 // the grid to start before the launch switches to claiming (100 us of the
 // 100 MHz constant clock; dispatching a full grid takes a few us).
@@ -52,6 +56,25 @@ constexpr uint32_t kArriveTicks = 10000u;
 constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
+
+// Static-grid sizes learned in this process: per (device, update kernel), the
+// blocks per CU below which no launch has yet been found not co-resident.  A
+// new context starts from min(occupancy query, learned value), so only the
+// first context of a process pays for a grid the device does not hold.
+std::mutex g_grid_mutex;
+std::map<std::pair<int, const void*>, int> g_grid_learned;
+
+int learned_blocks_per_cu(int dev, const void* fn, int query) {
+  std::lock_guard<std::mutex> lock(g_grid_mutex);
+  auto it = g_grid_learned.find({dev, fn});
+  return it == g_grid_learned.end() ? query : std::min(query, it->second);
+}
+
+void learn_blocks_per_cu(int dev, const void* fn, int per_cu) {
+  std::lock_guard<std::mutex> lock(g_grid_mutex);
+  auto it = g_grid_learned.find({dev, fn});
+  if (it == g_grid_learned.end() || per_cu < it->second) g_grid_learned[{dev, fn}] = per_cu;
+}
 
 // Workspace of f2v_train_static, the entry point for callers that cannot
 // allocate: a file-scope device array, one per GPU the library runs on, held
@@ -200,6 +223,7 @@ struct f2v_ctx {
   const Variant* var = nullptr;
   const void* update_fn = nullptr;  // var's update kernel for this d
   int update_grid = 0;      // grid of the static (dataflow) schedule: blocks_per_cu per CU
+  int dev = 0;              // device the context runs on
   int blocks_per_cu = 0;    // the occupancy limit, less one for every launch found not co-resident
   int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit or the job's size
   int cus = 0;
@@ -387,6 +411,8 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
   if ((he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c->update_fn, kBlock, 0)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("occupancy query: ") + hipGetErrorString(he));
   if (per_cu < 1) per_cu = 1;
+  c->dev = dev;
+  per_cu = learned_blocks_per_cu(dev, c->update_fn, per_cu);
   c->blocks_per_cu = per_cu;
   c->update_grid = per_cu * c->cus;
   c->fan_in = p->fan_in > 0 ? p->fan_in : kDefaultFanIn;
@@ -733,6 +759,7 @@ f2v_status f2v_check(f2v_ctx* c) {
     if (c->blocks_per_cu > 1) {
       --c->blocks_per_cu;
       c->update_grid = c->blocks_per_cu * c->cus;
+      learn_blocks_per_cu(c->dev, c->update_fn, c->blocks_per_cu);
     }
   }
   if (e[0] != 0) {
@@ -826,6 +853,25 @@ f2v_status f2v_walks(const int64_t* d_rowptr, const int32_t* d_colidx, int64_t n
   hipError_t e = f2v::launch_walks(d_rowptr, d_colidx, n, k, seed, static_cast<uint32_t>(epoch), d_list, d_len,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("walks: ") + hipGetErrorString(e));
+  return F2V_OK;
+}
+
+f2v_status f2v_selftest_publish(int32_t pairs, int32_t rounds, void* d_ws, size_t ws_bytes, uint32_t out[3],
+                                void* stream) {
+  if (pairs < 1 || pairs > 1024) return fail(nullptr, F2V_E_INVALID_ARG, "pairs must be in [1, 1024]");
+  if (rounds < 1 || rounds > (1 << 24)) return fail(nullptr, F2V_E_INVALID_ARG, "rounds must be in [1, 2^24]");
+  if (!d_ws || !out) return fail(nullptr, F2V_E_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(nullptr, F2V_E_INVALID_ARG, "d_ws must be 256-byte aligned");
+  const size_t need = size_t(pairs) * 512 + (2 * size_t(pairs) + 3) * sizeof(uint32_t);
+  if (ws_bytes < need)
+    return fail(nullptr, F2V_E_INVALID_ARG, "the self-test needs a buffer of " + std::to_string(need) + " bytes");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* rows = static_cast<float*>(d_ws);
+  uint32_t* words = reinterpret_cast<uint32_t*>(static_cast<char*>(d_ws) + size_t(pairs) * 512);
+  hipError_t e = f2v::launch_selftest_publish(rows, words, pairs, rounds, kMaxPolls, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, words + 2 * size_t(pairs), 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(nullptr, F2V_E_HIP, std::string("publication self-test: ") + hipGetErrorString(e));
   return F2V_OK;
 }
 

@@ -200,6 +200,10 @@ const Variant* find_variant(int d, bool bf16);
 // Host launchers of the prologue, init and loss helper kernels (f2v_kernels.hip).
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// Self-test of the cross-XCD publication protocol (rows [pairs][128] floats;
+// words: flags [pairs], acknowledgements [pairs], counters [3]).
+hipError_t launch_selftest_publish(float* rows, uint32_t* words, int32_t pairs, int32_t rounds, uint32_t max_polls,
+                                  hipStream_t st);
 hipError_t launch_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_t n, int64_t nnz,
                             uint32_t* flag, hipStream_t st);
 hipError_t launch_hub_base(const int64_t* rowptr, int64_t n, int32_t chunk, int32_t fan_in,

@@ -669,6 +669,65 @@ __global__ void k_signal(uint32_t* rec, uint32_t seq, uint32_t* err, const uint3
   }
 }
 
+// Self-test of the publication protocol the update kernel's dependency waits
+// rely on.  Pair p is workgroups 2p (writer) and 2p + 1 (reader) of one wave
+// each; workgroups go to the XCDs round robin, so the two sit on different
+// XCDs, whose L2 caches are not coherent with each other.  In round r the
+// writer stores a 512-byte row (64 lanes x two floats) with device-scope
+// stores, waits for their completion and stores r into the pair's flag; the
+// reader polls the flag with device-scope loads until it reads r, loads the
+// row with device-scope loads and compares every word with what round r
+// wrote, then stores r into the pair's acknowledgement, which the writer
+// awaits before round r + 1.  Exactly the update kernel's publication (row
+// stores, drain, flag store) and consumption (flag poll, row loads).  Every
+// poll is bounded; out[0] counts words read stale, out[1] polls that ran
+// into their bound, out[2] readers that finished all rounds.
+__device__ __forceinline__ uint32_t selftest_bits(int32_t p, int32_t r, int j) {
+  uint32_t h = static_cast<uint32_t>(r) * 2654435761u ^ (static_cast<uint32_t>(p) * 40503u + static_cast<uint32_t>(j));
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  return h & 0x3fffffffu;  // no NaN or infinity patterns
+}
+
+__global__ __launch_bounds__(64) void k_selftest_publish(float* rows, uint32_t* flags, uint32_t* acks,
+                                                         uint32_t* out, int32_t rounds, uint32_t max_polls) {
+  const int32_t p = static_cast<int32_t>(blockIdx.x >> 1);
+  const bool writer = (blockIdx.x & 1u) == 0u;
+  const int lane = static_cast<int>(threadIdx.x);
+  float* row = rows + static_cast<int64_t>(p) * 128 + 2 * lane;
+  for (int32_t r = 1; r <= rounds; ++r) {
+    const uint32_t* wait_on = writer ? acks + p : flags + p;
+    const uint32_t want = static_cast<uint32_t>(writer ? r - 1 : r);
+    uint32_t polls = 0;
+    while (ld_coherent_u32(wait_on) != want) {
+      if (++polls >= max_polls) {
+        if (lane == 0) atomicAdd(out + 1, 1u);
+        return;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    compiler_fence();
+    if (writer) {
+      const float v[2] = {__uint_as_float(selftest_bits(p, r, 2 * lane)),
+                          __uint_as_float(selftest_bits(p, r, 2 * lane + 1))};
+      store_coherent_f32<2>(row, v);
+      drain_memory();
+      if (lane == 0) st_coherent_u32(flags + p, static_cast<uint32_t>(r));
+    } else {
+      float v[2];
+      load_coherent<2, false>(row, v);
+      const bool bad = __float_as_uint(v[0]) != selftest_bits(p, r, 2 * lane) ||
+                       __float_as_uint(v[1]) != selftest_bits(p, r, 2 * lane + 1);
+      const uint64_t m = __ballot(bad);
+      if (lane == 0 && m != 0) atomicAdd(out, static_cast<uint32_t>(__popcll(m)));
+      drain_memory();
+      if (lane == 0) st_coherent_u32(acks + p, static_cast<uint32_t>(r));
+    }
+  }
+  if (!writer && lane == 0) atomicAdd(out + 2, 1u);
+}
+
 int grid_for(int64_t work, int threads) {
   int64_t g = (work + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -692,6 +751,16 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);
   hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + 2 * static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0,
                      st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_selftest_publish(float* rows, uint32_t* words, int32_t pairs, int32_t rounds, uint32_t max_polls,
+                                  hipStream_t st) {
+  // words: flags [pairs], acknowledgements [pairs], then the three counters
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * static_cast<int64_t>(pairs) + 3, 256)), dim3(256), 0, st, words,
+                     0u, 2 * static_cast<int64_t>(pairs) + 3);
+  hipLaunchKernelGGL(k_selftest_publish, dim3(2 * pairs), dim3(64), 0, st, rows, words, words + pairs,
+                     words + 2 * static_cast<int64_t>(pairs), rounds, max_polls);
   return hipGetLastError();
 }
 

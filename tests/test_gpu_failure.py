@@ -94,3 +94,28 @@ def test_oversubscribed_static_grid_claims_and_matches(monkeypatch):
     got = z.cpu().numpy()
     tr.close()
     assert np.array_equal(got, ref[-1])
+
+
+def test_grid_lowered_by_a_check_carries_to_new_contexts():
+    """The static grid a context ends with (after its checks lowered it for
+    launches found not co-resident) is where the next context with the same
+    update kernel starts in this process; an unrelated job's grid is bounded
+    by its own kernel's occupancy."""
+    g = gg.chung_lu(20000, 2.1, 20.0, 3)
+    p = dict(d=128, batch=128, s=5, force="sigmoid", lr0=0.02, seed=5)
+    Z0 = gg.init_embedding(g.n, p["d"], 3)
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(Z0, dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p))
+    start = tr.health()["blocks_per_cu"]
+    for e in range(3):
+        tr.epoch(e)
+        tr.check()
+    end = tr.health()
+    tr.close()
+    assert 1 <= end["blocks_per_cu"] <= start
+    assert start - end["blocks_per_cu"] == end["fallbacks"] or end["blocks_per_cu"] == 1
+    z2 = torch.from_numpy(np.ascontiguousarray(Z0, dtype=np.float32)).cuda()
+    tr2 = f2v.Trainer(rowptr, colidx, z2, lib_params(g, p))
+    assert tr2.health()["blocks_per_cu"] == end["blocks_per_cu"]
+    tr2.close()
