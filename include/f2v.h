@@ -314,7 +314,10 @@ typedef struct f2v_server f2v_server;
 f2v_status f2v_footprint(const f2v_params *p, size_t *bytes);
 
 /* Create a server (1 <= max_slots <= 256, hbm_budget > 0).  Allocates the
- * slots' streams and a small pinned host array for completion records. */
+ * slots' streams, eight streams for the concurrent update launches of pack
+ * graphs, sixteen argument-table buffers for packs (about 1 MiB each, device
+ * memory plus its pinned host source) and a small pinned host array for
+ * completion records. */
 f2v_status f2v_server_create(size_t hbm_budget, int32_t max_slots, f2v_server **out);
 
 /* Admit one job of `epochs` epochs (0 .. epochs-1) with params p
@@ -322,14 +325,24 @@ f2v_status f2v_server_create(size_t hbm_budget, int32_t max_slots, f2v_server **
  * f2v_init).  F2V_E_BUSY if no slot is free or the footprint does not fit the
  * remaining budget (the caller queues the job and retries).  pack == 0: the
  * run is issued at once on the slot's stream.  pack != 0: the job waits for
- * f2v_server_flush, which captures all waiting jobs into one HIP graph (each
- * job on its own stream) and starts it with one launch.  On success *job_id
- * identifies the job.  Validates the CSR (synchronises the slot's stream). */
+ * f2v_server_flush.  On success *job_id identifies the job.  Validates the
+ * CSR (synchronises the slot's stream). */
 f2v_status f2v_server_submit(f2v_server *s, const f2v_params *p, const int64_t *d_rowptr,
                              const int32_t *d_colidx, float *d_z, void *d_ws, size_t ws_bytes,
                              int32_t epochs, int32_t pack, uint64_t *job_id);
 
-/* Launch the packed jobs submitted since the last flush as one graph. */
+/* Launch the packed jobs submitted since the last flush.  They are grouped
+ * into packs of jobs of similar size (n * d within a factor of 4; up to 64
+ * jobs and 2048 (job, epoch) pairs per pack), and each pack is one HIP graph
+ * on the slot stream of its first job that runs its jobs in lockstep epochs.
+ * Per epoch the graph holds one launch of each prologue kernel for all of
+ * the pack's jobs, and one multi-job update launch per kernel instance (the
+ * jobs of one embedding width, precision and force family) on concurrent
+ * streams.  Every job keeps its own dynamic schedule on its own workgroups,
+ * so its result is the bits it gets alone.  Each job's completion record is
+ * written after its own last epoch.  A job of more than 2048 epochs runs
+ * alone on its slot's stream.  Waits for a running pack only when all
+ * sixteen table buffers are in use. */
 f2v_status f2v_server_flush(f2v_server *s);
 
 /* Non-blocking: report up to `cap` jobs that finished (done[i], status[i] =

@@ -90,7 +90,8 @@ void* g_scratch_ptr[kMaxScratchDevices] = {};
 struct Layout {
   size_t zbuf1, bbuf0, bbuf1, perm, word, bat, split_ids, pcol, ecnt, uoff, eoff, loff, negs, wreal,
       ereal, lreal, epre, areal, ebase, bstart, lstart, ngroups, units, hub_base, hub_cnt, hub_part, err, health, wcol, wlen,
-      csr_flag, init_rec, scan_scratch, scan_total, split_total, loss_part, loss_out, wave_stats, trace, ticket,
+      csr_flag, init_rec, scan_scratch, scan_total, split_total, loss_part, loss_blocks, loss_out, wave_stats, trace,
+      ticket,
       total;
   int64_t nb, tmap_cap, hub_slot_cap;
 };
@@ -154,6 +155,7 @@ Layout layout_of(const f2v_params& p) {
   L.scan_total = take(8);
   L.split_total = take(8);
   L.loss_part = take(size_t(n) * 16);
+  L.loss_blocks = take(size_t(f2v::kLossBlocks) * 16);
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
   L.trace = take(size_t(n) * 8);
@@ -560,19 +562,23 @@ f2v_status f2v_init(const f2v_params* p, const int64_t* d_rowptr, const int32_t*
   return F2V_OK;
 }
 
-f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
-  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+}  // extern "C"
+
+namespace f2v {
+
+// Host side of epoch `epoch` of context c: the prologue's and the update
+// kernel's arguments, and the buffer that is current after the epoch.  No
+// device work.
+f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs* A_out, int* next_out) {
   if (epoch < 0) return fail(&c->err, F2V_E_INVALID_ARG, "epoch must be >= 0");
   const f2v_params& p = c->p;
   if (p.lr_schedule == F2V_LR_LINEAR && epoch >= p.total_epochs)
     return fail(&c->err, F2V_E_INVALID_ARG, "epoch must be < total_epochs under the linear schedule");
   const Layout& L = c->L;
-  const hipStream_t s = c->stream;
   const bool bf16 = p.precision == F2V_BF16;
   const int slots = slots_of(c->var);
-  if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[0], s));
-
-  SetupArgs sa{};
+  SetupArgs& sa = *sa_out;
+  sa = SetupArgs{};
   sa.rowptr = c->rowptr;
   sa.colidx = c->colidx;
   sa.perm = c->at<int32_t>(L.perm);
@@ -614,17 +620,18 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;
-  HIP_TRY(c, f2v::launch_setup(sa, s));
-  // tree counters and early-sum flags start every epoch at zero
-  if (c->hub_total > 0) HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, c->hub_total, s));
+  sa.hub_cnt = c->at<uint32_t>(L.hub_cnt);
+  sa.hub_total = c->hub_total;
 
-  EpochArgs A{};
+  EpochArgs& A = *A_out;
+  A = EpochArgs{};
   A.colidx = c->colidx;
   A.pcol = sa.pcol;
   A.wcol = sa.wcol;
   // the relaxed variant reads and writes one buffer in place
   const bool hogwild = p.schedule == F2V_SCHED_HOGWILD;
   const int next = hogwild ? c->cur : 1 - c->cur;
+  *next_out = next;
   A.relaxed = hogwild ? 1 : 0;
   if (bf16) {
     A.zc = c->bbuf[c->cur];
@@ -658,25 +665,44 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
   A.arrive_ticks = kArriveTicks;
   A.hold = c->hold;
   A.ticket = c->at<uint32_t>(L.ticket);
-  A.claim = 0;
   A.fan_in = c->fan_in;
   A.late_window = c->late_window;
   A.wave_stats = nullptr;
   A.trace = c->diagnostics ? c->at<uint32_t>(L.trace) : nullptr;
-  if (c->diagnostics && p.schedule != F2V_SCHED_STRICT && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves) {
+  if (c->diagnostics && p.schedule != F2V_SCHED_STRICT && int64_t(c->update_grid) * (kBlock / 64) <= kMaxStatWaves)
     A.wave_stats = c->at<uint64_t>(L.wave_stats);
-    c->stat_waves = int64_t(c->update_grid) * (kBlock / 64);
-  }
+  A.strict_batch = -1;
+  A.claim = p.schedule == F2V_SCHED_DYNAMIC ? 1 : 0;
+  return F2V_OK;
+}
+
+void epoch_commit(f2v_ctx* c, int next) { c->cur = next; }
+
+}  // namespace f2v
+
+extern "C" {
+
+f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
+  if (!c) return fail(nullptr, F2V_E_INVALID_ARG, "ctx is NULL");
+  const f2v_params& p = c->p;
+  const Layout& L = c->L;
+  const hipStream_t s = c->stream;
+  const int slots = slots_of(c->var);
+  SetupArgs sa;
+  EpochArgs A;
+  int next = 0;
+  f2v_status st = f2v::epoch_prepare(c, epoch, &sa, &A, &next);
+  if (st != F2V_OK) return st;
+  if (A.wave_stats) c->stat_waves = int64_t(c->update_grid) * (kBlock / 64);
+  if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+  HIP_TRY(c, f2v::launch_setup(sa, s));
   if (c->record_events) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+  f2v::PackArgs none{};
+  void* args[] = {&A, &none};
   if (p.schedule == F2V_SCHED_DYNAMIC) {
-    A.strict_batch = -1;
-    A.claim = 1;
-    void* args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->dynamic_grid), dim3(kBlock), args, 0, s));
-  } else if (p.schedule == F2V_SCHED_DATAFLOW || hogwild) {
+  } else if (p.schedule == F2V_SCHED_DATAFLOW || p.schedule == F2V_SCHED_HOGWILD) {
     // static round robin; the kernel checks co-residency and claims if needed
-    A.strict_batch = -1;
-    void* args[] = {&A};
     HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s));
   } else {
     const int64_t groups_hint = (p.batch + slots - 1) / slots;
@@ -689,7 +715,6 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
       A.strict_batch = static_cast<int32_t>(k);
       for (int part = 0; part < (c->nsplit > 0 ? 2 : 1); ++part) {
         A.strict_late = part;
-        void* args[] = {&A};
         HIP_TRY(c, hipLaunchKernel(c->update_fn, dim3(grid), dim3(kBlock), args, 0, s));
       }
     }
@@ -698,7 +723,7 @@ f2v_status f2v_epoch(f2v_ctx* c, int32_t epoch) {
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->timed = true;
   }
-  c->cur = next;
+  f2v::epoch_commit(c, next);
   return F2V_OK;
 }
 
@@ -790,7 +815,11 @@ f2v_status f2v_loss(f2v_ctx* c, double out[3]) {
   A.z = p.precision == F2V_BF16 ? static_cast<const void*>(c->bbuf[c->cur])
                                 : static_cast<const void*>(c->zbuf[c->cur]);
   A.part = c->at<double>(c->L.loss_part);
+  A.block_part = c->at<double>(c->L.loss_blocks);
   A.out = c->at<double>(c->L.loss_out);
+  A.split_ids = c->at<int32_t>(c->L.split_ids);
+  A.nsplit = c->nsplit;
+  A.chunk = p.chunk;
   A.n = p.n;
   A.d = p.d;
   A.s = p.s;
@@ -905,5 +934,21 @@ hipStream_t ctx_stream(const f2v_ctx* c) { return c->stream; }
 uint32_t* ctx_err_word(f2v_ctx* c) { return c->at<uint32_t>(c->L.err); }
 const uint32_t* ctx_vertex_words(const f2v_ctx* c) { return c->at<uint32_t>(c->L.word); }
 int64_t ctx_n(const f2v_ctx* c) { return c->p.n; }
+// The multi-job update instance of the context's kernel, and its dynamic grid.
+const void* ctx_pack_fn(const f2v_ctx* c) {
+  const int fam = force_family(c->p.force);
+  return c->p.d == c->var->g * c->var->v * c->var->r ? c->var->pack_full[fam] : c->var->pack[fam];
+}
+int ctx_dynamic_grid(const f2v_ctx* c) { return c->dynamic_grid; }
+int ctx_schedule(const f2v_ctx* c) { return c->p.schedule; }
+// f2v_sync_embedding on another stream (the serving form's pack stream).
+hipError_t ctx_sync_embedding_on(f2v_ctx* c, hipStream_t st) {
+  if (c->p.precision == F2V_FP32 && c->cur != 0) {
+    const hipError_t e = launch_copy_f32(c->zbuf[0], c->zbuf[c->cur], c->p.n * int64_t(c->p.d), st);
+    if (e != hipSuccess) return e;
+    c->cur = 0;
+  }
+  return hipSuccess;
+}
 
 }  // namespace f2v

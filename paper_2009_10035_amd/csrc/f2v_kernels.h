@@ -125,6 +125,17 @@ struct EpochArgs {
                             // in place: the asynchronous variant); 0: synchronous
 };
 
+// Jobs of one multi-job update launch: job j owns the launch's workgroups
+// [block_start[j], block_start[j + 1]) and runs the dynamic schedule of its
+// own epoch (tab[j], device memory) on them.  Single-job launches pass
+// njobs = 0.
+constexpr int kMaxPackJobs = 64;
+struct PackArgs {
+  const EpochArgs* tab;
+  int32_t njobs;
+  int32_t block_start[kMaxPackJobs + 1];
+};
+
 // Prologue of an epoch (random partition, negatives, split-row lists, work
 // units).
 struct SetupArgs {
@@ -164,6 +175,8 @@ struct SetupArgs {
   int32_t feistel_half;
   uint32_t feistel_mask;
   const uint32_t* err;      // the context's error record: set = do nothing (k_walks: may be nullptr)
+  uint32_t* hub_cnt;        // tree counters and early-sum flags, reset every epoch
+  int64_t hub_total;        // their number
 };
 
 struct LossArgs {
@@ -171,12 +184,17 @@ struct LossArgs {
   const int32_t* colidx;
   const void* z;            // float or bf16 rows
   double* part;             // [n][2] per-vertex (attractive, repulsive) sums
+  double* block_part;       // [kLossBlocks][2] partial sums of the reduction's first level
   double* out;              // [3] total, attractive, repulsive
-  int64_t n;
-  int32_t d, s, force;
+  const int32_t* split_ids; // [nsplit] the rows of degree above `chunk`, taken first
+  int64_t n, nsplit;
+  int32_t d, s, force, chunk;
   float eps;
   uint64_t seed;
 };
+
+// Blocks of the first level of the loss's fixed-order reduction.
+constexpr int kLossBlocks = 1024;
 
 // Kernel variant of one embedding width: G lanes per row, V consecutive
 // elements per lane and load, R loads per lane to cover a row.  One update
@@ -185,8 +203,10 @@ struct LossArgs {
 struct Variant {
   int g, v, r;
   bool bf16;
-  const void* update[3];       // __global__ void(EpochArgs), any d <= g * v * r
+  const void* update[3];       // __global__ void(EpochArgs, PackArgs), any d <= g * v * r
   const void* update_full[3];  // the same for d = g * v * r (no lane past the row's end)
+  const void* pack[3];         // the multi-job instances (their jobs' EpochArgs from PackArgs)
+  const void* pack_full[3];
   const void* loss;            // __global__ void(LossArgs)
 };
 
@@ -199,6 +219,9 @@ const Variant* find_variant(int d, bool bf16);
 
 // Host launchers of the prologue, init and loss helper kernels (f2v_kernels.hip).
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st);
+// The prologue of several jobs' epochs in one launch per kernel: d_tab
+// [njobs] in device memory, h_tab the same on the host (for grid sizes).
+hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int njobs, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // Self-test of the cross-XCD publication protocol (rows [pairs][128] floats;
 // words: flags [pairs], acknowledgements [pairs], counters [3]).

@@ -1,6 +1,8 @@
 // Epoch prologue (random partition, shared negatives, ticket map), init-time
 // helpers (CSR check, split-row bookkeeping, bf16 copies) and the loss
 // reduction.
+#include <algorithm>
+
 #include "f2v_device.h"
 #include "f2v_kernels.h"
 
@@ -74,7 +76,9 @@ __device__ __forceinline__ void walk_positions(const Feistel& f, int64_t n, int 
 
 // K1: partition (position -> vertex, vertex -> batch word) and the shared
 // negatives of every batch.
-__global__ void k_setup_positions(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_setup_positions(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed: keep its words
   const Feistel f{A.seed, A.epoch, A.feistel_half, A.feistel_mask, A.n};
   const int64_t nneg = static_cast<int64_t>(A.nb) * A.s;
@@ -101,8 +105,10 @@ __global__ void k_setup_positions(SetupArgs A) {
 // walk has taken 4k steps (fewer than k vertices may be reachable) or it
 // reaches a vertex without neighbours.  One thread per vertex; the list is
 // built in place in the output (a thread reads back only its own stores).
-__global__ void k_walks(SetupArgs A) {
-  if (A.err && *A.err != 0u) return;  // an earlier epoch failed
+template <bool MULTI>
+__global__ void k_walks(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
+  if (A.walk_k <= 0 || (A.err && *A.err != 0u)) return;  // no walks, or an earlier epoch failed
   const int32_t k = A.walk_k;
   for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < A.n;
        u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -176,7 +182,9 @@ __device__ __forceinline__ int64_t reorder_list(const SetupArgs& A, int32_t k, i
 // depend only on the list and the partition.  A wave takes four rows at a
 // time: rows of at most kSmallSplit entries are done by 16 lanes each, at
 // once; longer ones by the whole wave, one after the other.
-__global__ void k_split_lists(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_split_lists(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4, l16 = lane & 15;
@@ -225,7 +233,9 @@ constexpr int kSortRowsPerWave = 8;
 // after the other.  Parts
 // longer than kSortLateMax, or windows wider than kSortLateWindow, keep their
 // order.
-__global__ void k_sort_late(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_sort_late(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -314,11 +324,14 @@ __device__ int64_t scan_positions(const SetupArgs& A, int64_t lo, int64_t hi, in
 // K2: one block per batch: in position order, the offsets of each row's
 // whole, early and late units among the batch's units of that kind, and the
 // batch's counts of each kind.
-__global__ void k_batch_units(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_batch_units(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
   const int32_t k = blockIdx.x;
+  if (k >= A.nb) return;  // a pack launch covers the most batches of its jobs
   const int64_t lo = static_cast<int64_t>(k) * A.b;
   const int64_t hi = lo + A.b < A.n ? lo + A.b : A.n;
   // whole and late counts in one scan: the halves never carry into each other
@@ -346,7 +359,9 @@ __device__ __forceinline__ int32_t early_home(int32_t k, int32_t window) {
 // K3: one block: per batch, the units of its first part (its whole units
 // and the early units it holds), the first ticket of the batch, of its second
 // part and of its early units, and the group count.
-__global__ void k_batch_starts(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_batch_starts(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed
   __shared__ int64_t lds[kScanThreads];
   __shared__ int64_t tile_total;
@@ -409,7 +424,9 @@ __global__ void k_batch_starts(SetupArgs A) {
 // K4: work units in ticket order.  Threads [0, n) write the units of one
 // position; threads [n, n + 2*nb*slots) mark the padding tickets at the end of
 // each batch's two parts.
-__global__ void k_tickets(SetupArgs A) {
+template <bool MULTI>
+__global__ void k_tickets(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
   if (*A.err != 0u) return;  // an earlier epoch failed
   const int64_t pad_threads = 2 * static_cast<int64_t>(A.nb) * A.slots;
   const int64_t total = A.n + pad_threads;
@@ -566,13 +583,12 @@ __global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t count) {
 
 // Deterministic FP64 reduction of the per-vertex loss parts: thread t sums
 // vertices t, t + 1024, ... in order, then a fixed tree over the threads.
-__global__ void k_loss_reduce(const double* part, int64_t n, double* out) {
-  __shared__ double sa[kScanThreads], sr[kScanThreads];
-  double a = 0.0, r = 0.0;
-  for (int64_t u = threadIdx.x; u < n; u += blockDim.x) {
-    a += part[2 * u];
-    r += part[2 * u + 1];
-  }
+// Fixed-order two-level sum of the per-vertex loss parts: block k of the
+// first level sums the contiguous range of vertices [k n / B, (k+1) n / B)
+// (per thread in vertex order, then a tree over the block's threads); one
+// block then sums the B partials the same way.  The association depends only
+// on n, so the result has the same bits on every run.
+__device__ void block_sum2(double a, double r, double* sa, double* sr, double* out2) {
   sa[threadIdx.x] = a;
   sr[threadIdx.x] = r;
   __syncthreads();
@@ -584,9 +600,35 @@ __global__ void k_loss_reduce(const double* part, int64_t n, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = sa[0] + sr[0];
-    out[1] = sa[0];
-    out[2] = sr[0];
+    out2[0] = sa[0];
+    out2[1] = sr[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_loss_reduce_blocks(const double* part, int64_t n, double* block_part) {
+  __shared__ double sa[256], sr[256];
+  const int64_t lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
+  double a = 0.0, r = 0.0;
+  for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
+    a += part[2 * u];
+    r += part[2 * u + 1];
+  }
+  block_sum2(a, r, sa, sr, block_part + 2 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_loss_reduce(const double* block_part, int32_t blocks, double* out) {
+  __shared__ double sa[256], sr[256];
+  __shared__ double t[2];
+  double a = 0.0, r = 0.0;
+  for (int k = threadIdx.x; k < blocks; k += blockDim.x) {
+    a += block_part[2 * k];
+    r += block_part[2 * k + 1];
+  }
+  block_sum2(a, r, sa, sr, t);
+  if (threadIdx.x == 0) {
+    out[0] = t[0] + t[1];
+    out[1] = t[0];
+    out[2] = t[1];
   }
 }
 
@@ -728,6 +770,16 @@ __global__ __launch_bounds__(64) void k_selftest_publish(float* rows, uint32_t* 
   if (!writer && lane == 0) atomicAdd(out + 2, 1u);
 }
 
+// Tree counters and early-sum flags of split rows start every epoch at zero
+// (device-scope stores: they are next used by device-scope atomics and polls).
+template <bool MULTI>
+__global__ void k_reset_hub(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < A.hub_total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    st_coherent_u32(A.hub_cnt + i, 0u);
+}
+
 int grid_for(int64_t work, int threads) {
   int64_t g = (work + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -737,20 +789,55 @@ int grid_for(int64_t work, int threads) {
 
 }  // namespace
 
-hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
-  const int64_t nneg = static_cast<int64_t>(a.nb) * a.s;
-  const int64_t walkers = walk_threads(a.n);
-  hipLaunchKernelGGL(k_setup_positions, dim3(grid_for(walkers > nneg ? walkers : nneg, 256)), dim3(256), 0, st, a);
-  if (a.walk_k > 0) hipLaunchKernelGGL(k_walks, dim3(grid_for(a.n, 256)), dim3(256), 0, st, a);
-  if (a.nsplit > 0) {
-    hipLaunchKernelGGL(k_split_lists, dim3(grid_for(a.nsplit * 16, 256)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_sort_late, dim3(grid_for(a.nsplit * (64 / kSortRowsPerWave), 256)), dim3(256), 0, st,
-                       a);
+// The prologue's launches: the single-job instances take the arguments by
+// value, the multi-job ones from the table (blockIdx.y = job).
+template <bool MULTI>
+void launch_prologue(const SetupArgs& one, const SetupArgs* d_tab, unsigned y, int64_t positions, int64_t walks,
+                     int64_t splits, int64_t batches, int batch_threads, int64_t tickets, int64_t hub,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_positions<MULTI>, dim3(grid_for(positions, 256), y), dim3(256), 0, st, one, d_tab);
+  if (walks > 0) hipLaunchKernelGGL(k_walks<MULTI>, dim3(grid_for(walks, 256), y), dim3(256), 0, st, one, d_tab);
+  if (splits > 0) {
+    hipLaunchKernelGGL(k_split_lists<MULTI>, dim3(grid_for(splits * 16, 256), y), dim3(256), 0, st, one, d_tab);
+    hipLaunchKernelGGL(k_sort_late<MULTI>, dim3(grid_for(splits * (64 / kSortRowsPerWave), 256), y), dim3(256), 0,
+                       st, one, d_tab);
   }
-  hipLaunchKernelGGL(k_batch_units, dim3(a.nb), dim3(a.b >= 1024 ? 1024 : 256), 0, st, a);
-  hipLaunchKernelGGL(k_batch_starts, dim3(1), dim3(kScanThreads), 0, st, a);
-  hipLaunchKernelGGL(k_tickets, dim3(grid_for(a.n + 2 * static_cast<int64_t>(a.nb) * a.slots, 256)), dim3(256), 0,
-                     st, a);
+  hipLaunchKernelGGL(k_batch_units<MULTI>, dim3(static_cast<unsigned>(batches), y), dim3(batch_threads), 0, st, one,
+                     d_tab);
+  hipLaunchKernelGGL(k_batch_starts<MULTI>, dim3(1, y), dim3(kScanThreads), 0, st, one, d_tab);
+  hipLaunchKernelGGL(k_tickets<MULTI>, dim3(grid_for(tickets, 256), y), dim3(256), 0, st, one, d_tab);
+  if (hub > 0) hipLaunchKernelGGL(k_reset_hub<MULTI>, dim3(grid_for(hub, 256), y), dim3(256), 0, st, one, d_tab);
+}
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
+  return launch_setup_pack(nullptr, &a, 1, st);
+}
+
+// One launch per prologue kernel over `njobs` jobs (blockIdx.y = job; with
+// d_tab = nullptr, the single job h_tab[0] passed by value).  Each grid covers
+// the largest need among the jobs; the kernels stride over their own job's
+// sizes, so the surplus blocks of a smaller job find nothing to do.
+hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int njobs, hipStream_t st) {
+  int64_t positions = 0, walks = 0, splits = 0, batches = 0, tickets = 0, hub = 0;
+  int batch_threads = 256;
+  for (int j = 0; j < njobs; ++j) {
+    const SetupArgs& a = h_tab[j];
+    const int64_t nneg = static_cast<int64_t>(a.nb) * a.s, walkers = walk_threads(a.n);
+    positions = std::max(positions, walkers > nneg ? walkers : nneg);
+    if (a.walk_k > 0) walks = std::max(walks, a.n);
+    splits = std::max(splits, a.nsplit);
+    batches = std::max(batches, static_cast<int64_t>(a.nb));
+    tickets = std::max(tickets, a.n + 2 * static_cast<int64_t>(a.nb) * a.slots);
+    hub = std::max(hub, a.hub_total);
+    if (a.b >= 1024) batch_threads = 1024;
+  }
+  const SetupArgs one = d_tab ? SetupArgs{} : h_tab[0];
+  const unsigned y = static_cast<unsigned>(njobs);
+  if (d_tab) {
+    launch_prologue<true>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, hub, st);
+  } else {
+    launch_prologue<false>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, hub, st);
+  }
   return hipGetLastError();
 }
 
@@ -811,7 +898,8 @@ hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t count, hipStr
 }
 
 hipError_t launch_loss_reduce(const LossArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(kScanThreads), 0, st, a.part, a.n, a.out);
+  hipLaunchKernelGGL(k_loss_reduce_blocks, dim3(kLossBlocks), dim3(256), 0, st, a.part, a.n, a.block_part);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, a.block_part, kLossBlocks, a.out);
   return hipGetLastError();
 }
 
@@ -860,7 +948,7 @@ hipError_t launch_walks(const int64_t* rowptr, const int32_t* colidx, int64_t n,
   a.wcol = list;
   a.wlen = len;
   a.err = nullptr;
-  hipLaunchKernelGGL(k_walks, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_walks<false>, dim3(grid_for(n, 256)), dim3(256), 0, st, a, static_cast<const SetupArgs*>(nullptr));
   return hipGetLastError();
 }
 

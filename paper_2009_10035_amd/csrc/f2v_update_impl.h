@@ -701,19 +701,32 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
   }
 }
 
-template <int G, int V, int R, bool BF16, bool FULL, int FAM>
+// MULTI: a launch over several jobs (P), each on its own range of workgroups
+// with its own EpochArgs; otherwise one job (A1).
+template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI>
 // Packed bf16 rows with one row per wave: sixteen rows in flight need more
 // registers than six waves per SIMD leave; the compiler is held to that
 // occupancy (a few values of the unit loop go to scratch).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && BF16 ? 6 : 1))) void k_update(EpochArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && BF16 ? 6 : 1))) void k_update(
+    EpochArgs A1, PackArgs P) {
   constexpr int S = 64 / G;
+  int job_block = static_cast<int>(blockIdx.x), job_blocks = static_cast<int>(gridDim.x);
+  const EpochArgs* Ap = &A1;
+  if constexpr (MULTI) {
+    int j = 0;
+    while (j + 1 < P.njobs && static_cast<int>(blockIdx.x) >= P.block_start[j + 1]) ++j;
+    Ap = P.tab + j;
+    job_block -= P.block_start[j];
+    job_blocks = P.block_start[j + 1] - P.block_start[j];
+  }
+  const EpochArgs& A = *Ap;
   // per-wave LDS for the reordered entries of a step (64 * kIdxPerLane words)
   __shared__ uint32_t order_lds[4][64 * ListShape<G>::kIdxPerLane];
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
   // wave-uniform (so that with one row per wave the unit records are scalar loads)
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(job_block * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int nwaves = job_blocks * (blockDim.x >> 6);
   uint32_t* order = order_lds[threadIdx.x >> 6];
   // an earlier epoch of this context gave up on a wait: leave its vertex
   // words as they are for the post-mortem
@@ -792,21 +805,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
 // Loss of Eq. 2 on the rows `z`: per vertex, FP32 pair terms summed in FP64
 // over its CSR neighbours (attractive part) and its s fixed loss negatives
 // (repulsive part).
+
+// Rows of a loss step: sixteen packed bf16 rows (one dword per lane) with one
+// row per wave, else eight.
+template <int G, bool BF16>
+struct LossRows {
+  static constexpr int value = (BF16 && G == 64) ? 16 : 8;
+};
+
+// Row `v` (-1: none) of the loss step's batch, lane l's part: packed bf16
+// dwords or widened floats.
+template <int G, int V, int R, bool BF16, bool PACKED>
+__device__ __forceinline__ void loss_load(const typename Elem<BF16>::T* z, int32_t v, int d, int l,
+                                          float (&y)[R][V], uint32_t (&yp)[R]) {
+  if constexpr (PACKED) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e0 = (r * G + l) * V;
+      yp[r] = (v >= 0 && e0 < d) ? *reinterpret_cast<const uint32_t*>(z + static_cast<int64_t>(v) * d + e0) : 0u;
+    }
+  } else if (v >= 0) {
+    load_row<G, V, R, BF16>(z, v, d, l, false, y);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int i = 0; i < V; ++i) y[r][i] = 0.0f;
+  }
+}
+
+// Per-lane partial of the pair with row `a` (packed rows widened here).
+template <int R, int V, bool PACKED>
+__device__ __forceinline__ float loss_partial(int32_t force, const float (&a)[R][V], const float (&y)[R][V],
+                                              const uint32_t (&yp)[R]) {
+  if constexpr (PACKED) {
+    float t[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      t[r][0] = __uint_as_float(yp[r] << 16);
+      t[r][1] = __uint_as_float(yp[r] & 0xffff0000u);
+    }
+    return pair_partial<R, V>(force, a, t);
+  } else {
+    return pair_partial<R, V>(force, a, y);
+  }
+}
+
 template <int G, int V, int R, bool BF16>
 __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
   using T = typename Elem<BF16>::T;
   constexpr int S = 64 / G;
   constexpr int K = LossShape<G>::kIdxPerLane;
   constexpr int kStep = LossShape<G>::kStep;
+  constexpr int U = LossRows<G, BF16>::value;
+  constexpr bool kPacked = BF16 && V == 2 && U == 16;
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
   const int64_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t nwaves = gridDim.x * (blockDim.x >> 6);
   const T* z = static_cast<const T*>(A.z);
   const int holder0 = slot * G;
-  for (int64_t base = wave * S; base < A.n; base += nwaves * S) {
-    const int64_t u = base + slot;
-    const bool active = u < A.n;
+  // The rows above `chunk` entries (the long ones) first, spread over the
+  // waves; then every other row.  Each vertex's sum keeps its own entry
+  // order, so the order in which vertices are taken changes nothing.
+  const int64_t split_groups = (A.nsplit + S - 1) / S;
+  const int64_t groups = split_groups + (A.n + S - 1) / S;
+  for (int64_t t = wave; t < groups; t += nwaves) {
+    int64_t u;
+    bool active;
+    if (t < split_groups) {
+      const int64_t i = t * S + slot;
+      active = i < A.nsplit;
+      u = active ? A.split_ids[i] : 0;
+    } else {
+      u = (t - split_groups) * S + slot;
+      active = u < A.n && !(A.nsplit > 0 && A.rowptr[u + 1] - A.rowptr[u] > A.chunk);
+    }
     float a[R][V];
     if (active) {
       load_row<G, V, R, BF16>(z, u, A.d, l, false, a);
@@ -820,69 +894,51 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
     const int64_t r0 = active ? A.rowptr[u] : 0;
     const int64_t len = active ? A.rowptr[u + 1] - r0 : 0;
     if constexpr (G >= 16) {
-      // eight rows in flight, their eight dot products (or squared distances)
-      // reduced at once; after the reduction lane l of the group holds entry
+      // U rows in flight, their dot products (or squared distances) reduced
+      // eight at once; after a reduction lane l of the group holds entry
       // l % 8's, and the group's first eight lanes each add one entry's term
       double ta = 0.0, tr = 0.0;
       const int seg = l & 7;
       const bool keeper = l < 8;
-      for (int64_t off = 0; __any(active && off < len); off += 8) {
-        int32_t v[8];
+      // one pass per part: attraction over the row's neighbours, then
+      // repulsion from its s loss negatives
+      for (int part = 0; part < 2; ++part) {
+        const int64_t count = !active ? 0 : (part == 0 ? len : A.s);
+        for (int64_t off = 0; __any(off < count); off += U) {
+          int32_t v[U];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          v[q] = (active && off + q < len) ? A.colidx[r0 + off + q] : -1;
-          if constexpr (G == 64) v[q] = __builtin_amdgcn_readfirstlane(v[q]);
-        }
-        float y[8][R][V], dq[8];
+          for (int q = 0; q < U; ++q) {
+            v[q] = -1;
+            if (off + q < count) {
+              if (part == 0) {
+                v[q] = A.colidx[r0 + off + q];
+              } else {
+                const uint4 x = philox(static_cast<uint32_t>(u), static_cast<uint32_t>(static_cast<uint64_t>(u) >> 32),
+                                       static_cast<uint32_t>(off + q), kTagEval, A.seed);
+                v[q] = uniform_index(x.x, x.y, A.n);
+              }
+            }
+            if constexpr (G == 64) v[q] = __builtin_amdgcn_readfirstlane(v[q]);
+          }
+          float y[U][R][V];
+          uint32_t yp[U][R];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (v[q] >= 0) {
-            load_row<G, V, R, BF16>(z, v[q], A.d, l, false, y[q]);
-          } else {
+          for (int q = 0; q < U; ++q) loss_load<G, V, R, BF16, kPacked>(z, v[q], A.d, l, y[q], yp[q]);
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+          for (int h = 0; h < U / 8; ++h) {
+            float dq[8];
 #pragma unroll
-              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+            for (int q = 0; q < 8; ++q) dq[q] = loss_partial<R, V, kPacked>(A.force, a, y[8 * h + q], yp[8 * h + q]);
+            const float dl = group_sum8_scatter<G>(dq);
+            int32_t mine = -1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) mine = seg == q ? v[8 * h + q] : mine;
+            if (keeper && mine >= 0) {
+              if (part == 0) ta += static_cast<double>(attract_loss(A.force, dl));
+              else tr += static_cast<double>(repulse_loss(A.force, dl, A.eps));
+            }
           }
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
-        const float dl = group_sum8_scatter<G>(dq);
-        int32_t mine = -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) mine = seg == q ? v[q] : mine;
-        if (keeper && mine >= 0) ta += static_cast<double>(attract_loss(A.force, dl));
-      }
-      for (int32_t j0 = 0; j0 < A.s; j0 += 8) {
-        int32_t w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          w[q] = -1;
-          if (active && j0 + q < A.s) {
-            const uint4 x = philox(static_cast<uint32_t>(u), static_cast<uint32_t>(static_cast<uint64_t>(u) >> 32),
-                                   static_cast<uint32_t>(j0 + q), kTagEval, A.seed);
-            w[q] = uniform_index(x.x, x.y, A.n);
-          }
-        }
-        float y[8][R][V], dq[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (w[q] >= 0) {
-            load_row<G, V, R, BF16>(z, w[q], A.d, l, false, y[q]);
-          } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-              for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dq[q] = pair_partial<R, V>(A.force, a, y[q]);
-        const float dl = group_sum8_scatter<G>(dq);
-        int32_t mine = -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) mine = seg == q ? w[q] : mine;
-        if (keeper && mine >= 0) tr += static_cast<double>(repulse_loss(A.force, dl, A.eps));
       }
       // the eight keepers' sums, added in a fixed pattern (every keeper ends
       // with the same bits); lane 0 of the group stores them

@@ -3,18 +3,16 @@
 
 namespace f2v {
 
+#define F2V_UPDATE(G, V, R, B, FULL, M) \
+  {reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 0, M>), \
+   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 1, M>), \
+   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 2, M>)}
 #define F2V_VARIANT(G, V, R, B) \
-  Variant{G, V, R, B, \
-          {reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 0>), \
-           reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 1>), \
-           reinterpret_cast<const void*>(&k_update<G, V, R, B, false, 2>)}, \
-          {reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 0>), \
-           reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 1>), \
-           reinterpret_cast<const void*>(&k_update<G, V, R, B, true, 2>)}, \
+  Variant{G, V, R, B, F2V_UPDATE(G, V, R, B, false, false), F2V_UPDATE(G, V, R, B, true, false), \
+          F2V_UPDATE(G, V, R, B, false, true), F2V_UPDATE(G, V, R, B, true, true), \
           reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
 
 extern const Variant kVariants_f32_v4[] = {
-    F2V_VARIANT(1, 4, 1, false),  F2V_VARIANT(2, 4, 1, false),  F2V_VARIANT(4, 4, 1, false),
     F2V_VARIANT(8, 4, 1, false),  F2V_VARIANT(16, 4, 1, false), F2V_VARIANT(32, 4, 1, false),
     F2V_VARIANT(64, 4, 1, false), F2V_VARIANT(64, 4, 2, false), F2V_VARIANT(64, 4, 4, false)};
 extern const int kNumVariants_f32_v4 = sizeof(kVariants_f32_v4) / sizeof(kVariants_f32_v4[0]);

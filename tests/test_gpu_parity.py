@@ -187,17 +187,22 @@ def test_edge_cases(case):
 
 
 @pytest.mark.parametrize("force", ["sigmoid", "student_t"])
-def test_loss_parity(force):
+@pytest.mark.parametrize("d,precision", [(32, "fp32"), (128, "fp32"), (128, "bf16"), (2, "fp32")])
+def test_loss_parity(force, d, precision):
+    """Eq. 2 on the device against the oracle (the bf16 form: against the
+    oracle's bf16 emulation) on a graph whose long rows (above 32 entries)
+    the loss kernel takes first; every lane-group width and the packed bf16
+    rows."""
     g = gg.chung_lu(20000, 2.1, 16.0, 8)
-    p = dict(d=32, batch=384, s=5, force=force, lr0=0.02, seed=12)
-    Z0 = gg.init_embedding(g.n, 32, 4)
+    p = dict(d=d, batch=384, s=5, force=force, lr0=0.02, seed=12, precision=precision)
+    Z0 = gg.init_embedding(g.n, d, 4)
     rowptr, colidx = device_graph(g)
     z = torch.from_numpy(Z0).cuda()
     tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p))
     for e in range(3):
         got = np.array(tr.loss())
         tr.sync_embedding()
-        ref = oracle.loss(g, z.cpu().numpy(), oracle_params(p))
+        ref = oracle.loss(g, z.cpu().numpy(), oracle_params(p), emul=precision == "bf16")
         np.testing.assert_allclose(got, ref, rtol=1e-6)
         tr.epoch(e)
     tr.close()

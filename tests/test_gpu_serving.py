@@ -54,6 +54,30 @@ def test_each_result_same_alone_and_in_the_mix():
         assert np.array_equal(ref, mix["results"][j.request]), j.request
 
 
+def test_one_pack_of_many_jobs():
+    """Twenty small jobs admitted at once run as one pack: per epoch one
+    launch of each prologue kernel for all of them and one multi-job update
+    launch per kernel instance (six here: d in {2, 32, 128}, FP32 and bf16),
+    with epochs from 2 to 5.  Each result is the single-job path's bits."""
+    rng = np.random.default_rng(9)
+    graphs = [gg.chung_lu(int(n), 2.1, 12.0, seed=40 + i) for i, n in enumerate([600, 2500, 5000, 11000])]
+    jobs = []
+    for r in range(20):
+        d = [2, 32, 128][r % 3]
+        jobs.append(JobSpec(request=r, arrival=0.0, graph=graphs[int(rng.integers(len(graphs)))], d=d,
+                            precision="bf16" if (r // 3) % 2 else "fp32",
+                            force="student_t" if d == 2 else "sigmoid", epochs=2 + r % 4, seed=300 + r))
+    srv = DeviceServer(hbm_budget=8 << 30, max_slots=20)
+    mix = run_requests(jobs, srv, keep=[j.request for j in jobs])
+    srv.close()
+    assert mix["jobs"] == len(jobs) and mix["failed"] == 0 and mix["retried"] == 0
+    for j in jobs:
+        z0 = f2v.random_embedding(j.graph.n, j.d, 12345 + j.request).cpu().numpy()
+        p = dict(d=j.d, batch=j.batch, s=j.s, force=j.force, lr0=j.lr0, seed=j.seed, precision=j.precision)
+        ref = gpu_run(j.graph, z0, p, j.epochs, snapshots=False, schedule="dynamic")[-1]
+        assert np.array_equal(ref, mix["results"][j.request]), j.request
+
+
 def test_mix_results_match_the_oracle():
     """Every job of a served mix against the FP64 oracle run on the same
     start: FP32 jobs within 1e-5 (or 10x the oracle's own response to a
