@@ -163,7 +163,10 @@ f2v_status f2v_step_size(const f2v_params *p, int32_t epoch, float *eta);
  * n, nnz, d, b, s, precision and chunk; independent of the graph's degrees). */
 f2v_status f2v_workspace_size(const f2v_params *p, size_t *bytes);
 
-/* Create a context on the current HIP device.
+/* Create a context on the current HIP device for the problem of Section 2.1
+ * (graph G(V, E) with binary symmetric adjacency A, embedding Z of n rows of
+ * d) and the inputs of Algorithm 1 (b, s, the step size eta, the random
+ * partition per epoch).
  *   d_rowptr : int64[n+1] CSR row offsets (device)
  *   d_colidx : int32[nnz] column indices (device); row u lists N(u)
  *   d_z      : float[n*d] row-major initial embedding (device, in/out).  FP32:
