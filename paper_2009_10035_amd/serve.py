@@ -39,6 +39,7 @@ class JobSpec:
     batch: int = 384
     s: int = 5
     lr0: float = 0.02
+    walk_length: int = 0    # > 0: rForce2Vec's random-walk neighbourhoods (Algorithm 3)
 
     @property
     def updates(self) -> int:
@@ -47,7 +48,7 @@ class JobSpec:
     def params(self) -> Params:
         return make_params(self.graph.n, self.graph.nnz, self.d, batch=self.batch, s=self.s,
                            force=self.force, precision=self.precision, lr0=self.lr0,
-                           schedule="dynamic", seed=self.seed)
+                           schedule="dynamic", seed=self.seed, walk_length=self.walk_length)
 
 
 def make_job_stream(num_jobs: int, rate: float, seed: int = 0, *, pool_size: int = 48,

@@ -78,6 +78,33 @@ def test_one_pack_of_many_jobs():
         assert np.array_equal(ref, mix["results"][j.request]), j.request
 
 
+def test_pack_of_models_and_walks():
+    """One pack mixing the Table 2 models, walk-mode jobs (rForce2Vec, k = 5)
+    and plain jobs: the multi-job prologue builds each job's own lists (walks
+    for some, none for others), and every result is the single-job path's
+    bits."""
+    graphs = [gg.chung_lu(int(n), 2.1, 10.0, seed=60 + i) for i, n in enumerate([1200, 3000, 6000])]
+    kinds = [("fr", 0), ("linlog", 0), ("forceatlas", 0), ("sigmoid", 5), ("student_t", 5), ("sigmoid", 0)]
+    jobs = []
+    for r in range(12):
+        force, walk = kinds[r % len(kinds)]
+        # a small step for the spring models, whose attraction grows with distance
+        jobs.append(JobSpec(request=r, arrival=0.0, graph=graphs[r % len(graphs)], d=32,
+                            precision="bf16" if r % 4 == 3 else "fp32", force=force, epochs=3, seed=500 + r,
+                            walk_length=walk, lr0=0.002 if force in ("fr", "linlog", "forceatlas") else 0.02))
+    srv = DeviceServer(hbm_budget=8 << 30, max_slots=12)
+    mix = run_requests(jobs, srv, keep=[j.request for j in jobs])
+    srv.close()
+    assert mix["jobs"] == len(jobs) and mix["failed"] == 0 and mix["retried"] == 0
+    for j in jobs:
+        z0 = f2v.random_embedding(j.graph.n, j.d, 12345 + j.request).cpu().numpy()
+        p = dict(d=j.d, batch=j.batch, s=j.s, force=j.force, lr0=j.lr0, seed=j.seed, precision=j.precision,
+                 walk_length=j.walk_length)
+        ref = gpu_run(j.graph, z0, p, j.epochs, snapshots=False, schedule="dynamic")[-1]
+        assert np.isfinite(ref).all(), (j.request, j.force)
+        assert np.array_equal(ref, mix["results"][j.request]), (j.request, j.force, j.walk_length)
+
+
 def test_mix_results_match_the_oracle():
     """Every job of a served mix against the FP64 oracle run on the same
     start: FP32 jobs within 1e-5 (or 10x the oracle's own response to a
