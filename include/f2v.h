@@ -142,14 +142,27 @@ typedef struct {
                              row), until k are found, 4k steps are taken or
                              the walk reaches a vertex without neighbours.
                              f2v_loss still sums over the CSR rows. */
+    int32_t stage_negatives; /* How a batch's s negative rows reach its units
+                             (Algorithm 2, second loop).  0 (default): they
+                             are the tail of every whole and late unit's list,
+                             read like neighbours through the caches.  1: a
+                             pass of their own before the neighbours, with the
+                             rows staged once per workgroup and batch in LDS
+                             and read there by the workgroup's other waves.
+                             2: the same pass with every unit reading the rows
+                             from memory (1 and 2 give the same bits; both
+                             differ from 0 in summation order only).  1 and 2
+                             need s * d <= 2048 and a schedule other than
+                             dynamic; measured slower than 0 on the
+                             benchmarked workloads. */
 } f2v_params;
 
 typedef struct f2v_ctx f2v_ctx;
 
 /* Fill `p` with defaults: b = 384, s = 5, sigmoid, FP32, lr0 = 0.02 constant,
  * eps = 1e-3, random partition, dataflow schedule, chunk 0 (by size), seed 0,
- * late_window -1 and fan_in 0 (defaults), walk_length 0 (CSR rows).  n, nnz
- * and d must still be set. */
+ * late_window -1 and fan_in 0 (defaults), walk_length 0 (CSR rows),
+ * stage_negatives 0.  n, nnz and d must still be set. */
 void f2v_default_params(f2v_params *p);
 
 /* Host only.  Step size eta_e of epoch `epoch` (Algorithm 1 fixes only the

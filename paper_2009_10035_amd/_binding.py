@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("eps", ctypes.c_float), ("total_epochs", ctypes.c_int32), ("perm_mode", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("chunk", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("late_window", ctypes.c_int32), ("fan_in", ctypes.c_int32), ("walk_length", ctypes.c_int32),
+        ("stage_negatives", ctypes.c_int32),
     ]
 
 
@@ -141,7 +142,8 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
                 precision: str = "fp32", lr0: float = 0.02, lr_schedule: str = "const",
                 eps: float = 1e-3, total_epochs: int = 1, perm_mode: str = "random",
                 schedule: str = "dataflow", chunk: int | None = None, seed: int = 0,
-                late_window: int | None = None, fan_in: int | None = None, walk_length: int = 0) -> Params:
+                late_window: int | None = None, fan_in: int | None = None, walk_length: int = 0,
+                stage_negatives: int = 0) -> Params:
     p = Params()
     load().f2v_default_params(ctypes.byref(p))
     p.n, p.nnz, p.d, p.batch, p.s = n, nnz, d, batch, s
@@ -157,6 +159,7 @@ def make_params(n: int, nnz: int, d: int, *, batch: int = 384, s: int = 5, force
     if fan_in is not None:
         p.fan_in = fan_in
     p.walk_length = walk_length
+    p.stage_negatives = stage_negatives
     return p
 
 

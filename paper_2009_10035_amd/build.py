@@ -25,6 +25,9 @@ SOURCES = [
     "f2v_variants_f32_v1.hip",
     "f2v_variants_bf16_v4.hip",
     "f2v_variants_bf16_v2.hip",
+    "f2v_staged_f32_v1.hip",
+    "f2v_staged_f32_v2.hip",
+    "f2v_staged_bf16_v2.hip",
     "f2v_variants.cpp",
     "f2v_api.cpp",
     "f2v_server.cpp",

@@ -204,6 +204,17 @@ f2v_status validate(const f2v_params* p, std::string* msg) {
   if (p->late_window > (1 << 20)) return fail(msg, F2V_E_INVALID_ARG, "late_window must be at most 2^20");
   if (p->fan_in != 0 && (p->fan_in < 4 || p->fan_in > 64))
     return fail(msg, F2V_E_INVALID_ARG, "fan_in must be 0 (default) or in [4, 64]");
+  if (p->stage_negatives < 0 || p->stage_negatives > 2)
+    return fail(msg, F2V_E_INVALID_ARG, "stage_negatives must be 0, 1 or 2");
+  if (p->stage_negatives != 0 && int64_t{p->s} * p->d > f2v::kStageFloats)
+    return fail(msg, F2V_E_INVALID_ARG, "stage_negatives needs s * d <= 2048");
+  if (p->stage_negatives != 0 && p->schedule == F2V_SCHED_DYNAMIC)
+    return fail(msg, F2V_E_UNSUPPORTED, "stage_negatives is for the dataflow, strict and relaxed schedules");
+  if (p->stage_negatives != 0) {
+    const f2v::Variant* v = f2v::find_variant(p->d, p->precision == F2V_BF16);
+    if (v && !f2v::find_staged(v, f2v::force_family(p->force), p->d == v->g * v->v * v->r))
+      return fail(msg, F2V_E_UNSUPPORTED, "stage_negatives is not built for rows this wide");
+  }
   const Layout L = layout_of(*p);
   if (L.tmap_cap >= (int64_t{1} << 31)) return fail(msg, F2V_E_INVALID_ARG, "too many work units for int32 tickets");
   return F2V_OK;
@@ -389,7 +400,11 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
   c->ws = static_cast<char*>(d_ws);
   c->var = f2v::find_variant(p->d, p->precision == F2V_BF16);
   const int fam = f2v::force_family(p->force);
-  c->update_fn = p->d == c->var->g * c->var->v * c->var->r ? c->var->update_full[fam] : c->var->update[fam];
+  const bool full = p->d == c->var->g * c->var->v * c->var->r;
+  if (p->stage_negatives != 0)
+    c->update_fn = f2v::find_staged(c->var, fam, full);
+  else
+    c->update_fn = full ? c->var->update_full[fam] : c->var->update[fam];
   const bool bf16 = p->precision == F2V_BF16;
   c->zbuf[0] = d_z;
   c->zbuf[1] = bf16 ? nullptr : c->at<float>(L.zbuf1);
@@ -633,6 +648,7 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   const int next = hogwild ? c->cur : 1 - c->cur;
   *next_out = next;
   A.relaxed = hogwild ? 1 : 0;
+  A.stage = p.stage_negatives == 1 ? 1 : 0;
   if (bf16) {
     A.zc = c->bbuf[c->cur];
     A.zn = c->bbuf[next];

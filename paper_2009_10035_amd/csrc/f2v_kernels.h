@@ -123,7 +123,12 @@ struct EpochArgs {
                             // host-forced stall, to exercise the wait bound); -1: none
   int32_t relaxed;          // 1: no waits for rows of earlier batches (zc == zn, updated
                             // in place: the asynchronous variant); 0: synchronous
+  int32_t stage;            // staged-negatives instances: 1 copy the batch's negative rows
+                            // into LDS once per workgroup, 0 every unit reads them from memory
 };
+
+// Floats of one LDS slot of staged negative rows (s * d <= kStageFloats).
+constexpr int kStageFloats = 2048;
 
 // Jobs of one multi-job update launch: job j owns the launch's workgroups
 // [block_start[j], block_start[j + 1]) and runs the dynamic schedule of its
@@ -210,12 +215,22 @@ struct Variant {
   const void* loss;            // __global__ void(LossArgs)
 };
 
+// The staged-negatives instances of a variant (single job; compiled in
+// translation units of their own).
+struct StagedVariant {
+  int g, v, r;
+  bool bf16;
+  const void* fn[2][3];  // [full][force family]
+};
+
 // Update-kernel family of a force model (f2v_force): 0 sigmoid, 1 Student-t,
 // 2 Fruchterman-Reingold, LinLog and ForceAtlas.
 inline int force_family(int32_t force) { return force <= 1 ? force : 2; }
 
 // Variant for (d, bf16), or nullptr if d is not supported.
 const Variant* find_variant(int d, bool bf16);
+// Its staged-negatives update instance, or nullptr if there is none.
+const void* find_staged(const Variant* v, int family, bool full);
 
 // Host launchers of the prologue, init and loss helper kernels (f2v_kernels.hip).
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st);

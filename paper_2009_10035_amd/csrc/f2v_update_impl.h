@@ -22,6 +22,8 @@
 // tickets; waves take their tickets in increasing order, so in a co-resident
 // grid the lowest unfinished ticket can always proceed.
 #pragma once
+#include <type_traits>
+
 #include "f2v_device.h"
 #include "f2v_kernels.h"
 
@@ -452,6 +454,162 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
   }
 }
 
+// Staged negatives (the opt-in form of Algorithm 2's shared S_b: the s rows
+// every whole and late unit of batch k reads).  A workgroup keeps the rows of
+// up to two batches in LDS, in the slot of the batch's parity, with a tag per
+// slot: 0 empty, 2(k+1) being staged for batch k, 2(k+1)+1 ready for batch k.
+// The first wave of the workgroup to need batch k's rows claims an empty slot
+// or one ready for an older batch (a compare-and-swap on the tag; a slot
+// being staged is never taken over, so its stager is its only writer), loads
+// the rows as any unit would (waiting for rows of earlier batches), copies
+// them into the slot and marks it ready; the workgroup's other waves at batch
+// k read them from LDS.  A wave that finds the slot being staged polls its
+// tag for a bounded time, then reads from memory itself.  A reader checks
+// the tag again after each chunk of rows it copied out, before using them
+// (LDS operations of one wave take effect in order), so a slot taken over for
+// a later batch is never used.  The staged rows are the bits memory holds,
+// so where a unit's negatives come from changes nothing in its sum.
+constexpr uint32_t kStagePolls = 4096;
+struct NegStage {
+  float rows[2][kStageFloats];
+  uint32_t tag[2];
+};
+
+__device__ __forceinline__ uint32_t lds_tag(const uint32_t* t) {
+  return __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Repulsion of the group's row `a` from the batch's s shared negatives
+// (Algorithm 2, second loop) in a pass of its own, for the lane groups whose
+// unit takes the step (`has`); every such unit of the wave belongs to the same
+// batch k.  Entries in order j = 0 .. s-1, in chunks of UN rows; from LDS
+// (A.stage = 1) or from memory.
+template <int G, int V, int R, bool BF16, bool FULL, int kForce>
+__device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool has, int32_t k, bool wait, int l,
+                                                     NegStage& st, const float (&a)[R][V], float (&acc)[R][V],
+                                                     WaveCounters& wc) {
+  using T = typename Elem<BF16>::T;
+  constexpr int UN = Unroll<G, R, BF16>::value < 8 ? Unroll<G, R, BF16>::value : 8;
+  const int32_t s = A.s;
+  const uint64_t hm = __ballot(has);
+  if (hm == 0 || s <= 0) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t kw = __builtin_amdgcn_readfirstlane(__shfl(k, static_cast<int>(__builtin_ctzll(hm)), 64));
+  const int32_t* negs = A.negs + static_cast<int64_t>(kw) * s;
+  const int d = A.d;
+  // 0: rows from memory; 1: read the staged rows; 2: stage them
+  int mode = 0;
+  const int sl = kw & 1;
+  const uint32_t claimed = 2u * static_cast<uint32_t>(kw + 1), ready = claimed + 1u;
+  if (A.stage) {
+    int m = 0;
+    if (lane == 0) {
+      uint32_t t = lds_tag(&st.tag[sl]);
+      for (uint32_t polls = 0; t == claimed && polls < kStagePolls; ++polls) {
+        __builtin_amdgcn_s_sleep(1);
+        t = lds_tag(&st.tag[sl]);
+      }
+      if (t == ready) {
+        m = 1;
+      } else if (t == 0u || ((t & 1u) != 0u && t < claimed)) {
+        const uint32_t old = atomicCAS(&st.tag[sl], t, claimed);
+        m = old == t ? 2 : (old == ready ? 1 : 0);
+      }
+    }
+    mode = __builtin_amdgcn_readfirstlane(m);
+  }
+  const T* zc = static_cast<const T*>(A.zc);
+  const T* zn = static_cast<const T*>(A.zn);
+  float* slot_rows = st.rows[sl];
+  const bool writer = lane < G;  // one lane group copies the rows into the slot
+  for (int32_t j0 = 0; j0 < s; j0 += UN) {
+    int32_t vid[UN];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) vid[q] = j0 + q < s ? negs[j0 + q] : -1;
+    float y[UN][R][V];
+    bool staged = false;
+    if (mode == 1) {
+#pragma unroll
+      for (int q = 0; q < UN; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e0 = (r * G + l) * V;
+#pragma unroll
+          for (int i = 0; i < V; ++i)
+            y[q][r][i] = (vid[q] >= 0 && (FULL || e0 < d)) ? slot_rows[(j0 + q) * d + e0 + i] : 0.0f;
+        }
+      compiler_fence();
+      staged = __builtin_amdgcn_readfirstlane(static_cast<int>(lds_tag(&st.tag[sl]))) == static_cast<int>(ready);
+      if (!staged) mode = 0;  // the slot was taken over: the rest from memory
+    }
+    if (!staged) {
+      bool pend[UN], nxt[UN];
+#pragma unroll
+      for (int q = 0; q < UN; ++q) {
+        pend[q] = nxt[q] = false;
+        if (vid[q] >= 0) {
+          const uint32_t wd = ld_coherent_u32(A.word + vid[q]);
+          nxt[q] = static_cast<int32_t>(wd & ~kPublished) < kw;
+          pend[q] = wait && nxt[q] && (wd & kPublished) == 0u;
+        }
+      }
+      if (wait) wait_published<UN>(A, vid, pend, wc);
+#pragma unroll
+      for (int q = 0; q < UN; ++q) {
+        if (vid[q] >= 0) {
+          load_row<G, V, R, BF16, FULL>(nxt[q] ? zn : zc, vid[q], d, l, nxt[q], y[q]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
+        }
+      }
+      if (mode == 2 && writer) {
+#pragma unroll
+        for (int q = 0; q < UN; ++q)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int e0 = (r * G + l) * V;
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+              if (vid[q] >= 0 && (FULL || e0 < d)) slot_rows[(j0 + q) * d + e0 + i] = y[q][r][i];
+          }
+      }
+    }
+    float dq[UN], cq[UN];
+    bool rep[UN];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      dq[q] = pair_partial<R, V>(kForce, a, y[q]);
+      rep[q] = true;
+    }
+    batch_coefs<G, kForce, UN>(A, dq, rep, cq);
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      if (has && vid[q] >= 0) {
+        const float c = cq[q];
+        if constexpr (kForce == kSigmoid) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, y[q][r][i], acc[r][i]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[r][i] = fmaf(c, a[r][i] - y[q][r][i], acc[r][i]);
+        }
+      }
+    }
+  }
+  if (mode == 2) {
+    // the slot's rows are written (in order before the tag)
+    compiler_fence();
+    if (lane == 0) __hip_atomic_store(&st.tag[sl], ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
 // the early sum of a split row.  Bounded like wait_published.
 __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
@@ -494,9 +652,10 @@ __device__ __forceinline__ void store_partial(float* row, int d, int l, const fl
 // One work unit (see the unit kinds): accumulate its list, then either take
 // the step of Eq. 10 and publish the row (whole and late units) or add the
 // partial sum into the row's combining tree (early units).
-template <int G, int V, int R, bool BF16, bool FULL, int FAM>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool STAGE = false>
 __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
-                                             bool wait, uint32_t* order, WaveCounters& wc) {
+                                             bool wait, uint32_t* order, WaveCounters& wc,
+                                             NegStage* stage = nullptr) {
   using T = typename Elem<BF16>::T;
   const bool active = w.u >= 0;
   const int32_t u = active ? w.u : 0;
@@ -549,12 +708,20 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   }
 
   // attraction over the unit's neighbours, then (whole and late units)
-  // repulsion from the batch's shared negatives: Algorithm 2's two loops
+  // repulsion from the batch's shared negatives: Algorithm 2's two loops.
+  // The staged form takes the negatives first, in a pass of their own.
   const int32_t nneg = (active && !early) ? A.s : 0;
   const int32_t* list = ((w.kind & kUnitWalk) ? A.wcol : (w.kind & kUnitReordered) ? A.pcol : A.colidx) +
                         (active ? w.beg : 0);
   const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
-  accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a, acc, wc);
+  if constexpr (STAGE) {
+    accumulate_negatives<G, V, R, BF16, FULL, FAM>(A, active && !early, w.k, wait, l, *stage, a, acc, wc);
+    accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, nullptr, 0, w.k, wait, l, slot, order, a, acc,
+                                              wc);
+  } else {
+    accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a, acc,
+                                              wc);
+  }
 
   if (A.wave_stats && __any(late)) wc.wait_late += wc.wait - wait_before;
 
@@ -703,7 +870,7 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
 
 // MULTI: a launch over several jobs (P), each on its own range of workgroups
 // with its own EpochArgs; otherwise one job (A1).
-template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI, bool STAGE = false>
 // Packed bf16 rows with one row per wave: sixteen rows in flight need more
 // registers than six waves per SIMD leave; the compiler is held to that
 // occupancy (a few values of the unit loop go to scratch).
@@ -722,6 +889,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
   const EpochArgs& A = *Ap;
   // per-wave LDS for the reordered entries of a step (64 * kIdxPerLane words)
   __shared__ uint32_t order_lds[4][64 * ListShape<G>::kIdxPerLane];
+  // staged instances: the workgroup's two slots of negative rows
+  __shared__ std::conditional_t<STAGE, NegStage, uint32_t> stage_lds;
+  if constexpr (STAGE) {
+    if (threadIdx.x < 2) stage_lds.tag[threadIdx.x] = 0u;
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;
   // wave-uniform (so that with one row per wave the unit records are scalar loads)
@@ -783,7 +956,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
     nxt.u = -1;
     if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
     const int gnn = __builtin_amdgcn_readfirstlane(gn < gend ? following(gn) : gend);
-    process_unit<G, V, R, BF16, FULL, FAM>(A, cur, l, slot, wait, order, wc);
+    if constexpr (STAGE) {
+      process_unit<G, V, R, BF16, FULL, FAM, true>(A, cur, l, slot, wait, order, wc, &stage_lds);
+    } else {
+      process_unit<G, V, R, BF16, FULL, FAM>(A, cur, l, slot, wait, order, wc);
+    }
     cur = nxt;
     g = gn;
     gn = gnn;

@@ -7,6 +7,8 @@ extern const Variant kVariants_f32_v4[], kVariants_f32_v2[], kVariants_f32_v1[];
 extern const Variant kVariants_bf16_v4[], kVariants_bf16_v2[];
 extern const int kNumVariants_f32_v4, kNumVariants_f32_v2, kNumVariants_f32_v1;
 extern const int kNumVariants_bf16_v4, kNumVariants_bf16_v2;
+extern const StagedVariant kStaged_f32_v1[], kStaged_f32_v2[], kStaged_bf16_v2[];
+extern const int kNumStaged_f32_v1, kNumStaged_f32_v2, kNumStaged_bf16_v2;
 
 // Fewest lanes per row: 8.  Narrow rows still get several lanes (the extra
 // lanes hold no elements): fewer rows per wave means fewer rows of one wave
@@ -58,6 +60,18 @@ const Variant* find_variant(int d, bool bf16) {
   while (v0 > 1 && d % v0 != 0) v0 >>= 1;
   for (int v = v0; v <= 4; v <<= 1)
     if (const Variant* x = lookup(d, bf16, v)) return x;
+  return nullptr;
+}
+
+const void* find_staged(const Variant* v, int family, bool full) {
+  if (!v || family < 0 || family > 2) return nullptr;
+  const StagedVariant* tabs[] = {kStaged_f32_v1, kStaged_f32_v2, kStaged_bf16_v2};
+  const int counts[] = {kNumStaged_f32_v1, kNumStaged_f32_v2, kNumStaged_bf16_v2};
+  for (int t = 0; t < 3; ++t)
+    for (int i = 0; i < counts[t]; ++i) {
+      const StagedVariant& x = tabs[t][i];
+      if (x.g == v->g && x.v == v->v && x.r == v->r && x.bf16 == v->bf16) return x.fn[full ? 1 : 0][family];
+    }
   return nullptr;
 }
 

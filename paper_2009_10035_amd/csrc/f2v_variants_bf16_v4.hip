@@ -13,7 +13,6 @@ namespace f2v {
           reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
 
 extern const Variant kVariants_bf16_v4[] = {
-    F2V_VARIANT(8, 4, 1, true),  F2V_VARIANT(16, 4, 1, true), F2V_VARIANT(32, 4, 1, true),
     F2V_VARIANT(64, 4, 1, true), F2V_VARIANT(64, 4, 2, true), F2V_VARIANT(64, 4, 4, true)};
 extern const int kNumVariants_bf16_v4 = sizeof(kVariants_bf16_v4) / sizeof(kVariants_bf16_v4[0]);
 

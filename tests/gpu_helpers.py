@@ -24,7 +24,7 @@ def lib_params(g, p: dict, **over):
         eps=q.get("eps", 1e-3), total_epochs=q.get("total_epochs", 1),
         perm_mode=q.get("perm_mode", "random"), schedule=q.get("schedule", "dataflow"),
         chunk=q.get("chunk", 0), seed=q["seed"], late_window=q.get("late_window"), fan_in=q.get("fan_in"),
-        walk_length=q.get("walk_length", 0))
+        walk_length=q.get("walk_length", 0), stage_negatives=q.get("stage_negatives", 0))
 
 
 def oracle_params(p: dict, **over) -> oracle.OracleParams:

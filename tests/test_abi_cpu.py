@@ -84,6 +84,7 @@ def test_default_chunk_follows_graph_size():
     ("lr0", float("nan"), "F2V_E_INVALID_ARG"), ("eps", 1.0, "F2V_E_INVALID_ARG"),
     ("eps", -0.1, "F2V_E_INVALID_ARG"), ("perm_mode", 2, "F2V_E_INVALID_ARG"),
     ("schedule", 4, "F2V_E_INVALID_ARG"), ("chunk", -1, "F2V_E_INVALID_ARG"), ("nnz", -1, "F2V_E_INVALID_ARG"),
+    ("stage_negatives", 3, "F2V_E_INVALID_ARG"), ("stage_negatives", -1, "F2V_E_INVALID_ARG"),
 ])
 def test_validation(field, value, status):
     p = good()
@@ -147,3 +148,18 @@ def test_static_workspace_entry_refuses_oversize_jobs_on_the_host():
     p = good()
     st = lib.f2v_train_static(ctypes.cast(ctypes.pointer(p), ctypes.c_void_p), 256, 512, 1024, -1, 1, None)
     assert _binding.STATUS[st] == "F2V_E_INVALID_ARG"
+
+
+def test_staged_negatives_limits():
+    """The staged-negatives forms need the batch's rows to fit an LDS slot
+    (s * d <= 2048 floats) and a schedule whose waves a workgroup shares (not
+    the dynamic one); within that they are accepted."""
+    ok = f2v.make_params(1000, 8000, 128, s=10, stage_negatives=1)
+    assert f2v.workspace_size(ok) > 0
+    for stage in (1, 2):
+        with pytest.raises(f2v.F2VError) as ei:
+            f2v.workspace_size(f2v.make_params(1000, 8000, 128, s=17, stage_negatives=stage))
+        assert ei.value.name == "F2V_E_INVALID_ARG"
+        with pytest.raises(f2v.F2VError) as ei:
+            f2v.workspace_size(f2v.make_params(1000, 8000, 32, schedule="dynamic", stage_negatives=stage))
+        assert ei.value.name == "F2V_E_UNSUPPORTED"

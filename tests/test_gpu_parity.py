@@ -12,7 +12,8 @@ import torch
 import graphgen as gg
 import oracle
 import paper_2009_10035_amd as f2v
-from gpu_helpers import assert_parity, device_graph, gpu_run, lib_params, oracle_params, rel_fro, row_rel
+from gpu_helpers import (assert_parity, bf16_compare, device_graph, gpu_run, lib_params, oracle_params, rel_fro,
+                         row_rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +109,38 @@ def test_split_rows_late_window(window, fan_in):
         assert np.array_equal(x, y) and np.array_equal(x, z)
     ref = oracle.epoch(g, Z0, 0, oracle_params(p))
     assert_parity(a[0], ref, TOL, ROW_TOL_ONE_EPOCH)
+
+
+@pytest.mark.parametrize("d,force,precision,s", [
+    (128, "sigmoid", "fp32", 5), (128, "student_t", "bf16", 10), (32, "student_t", "fp32", 5),
+    (2, "student_t", "fp32", 5), (2, "sigmoid", "bf16", 64),
+])
+def test_staged_negatives(d, force, precision, s):
+    """The opt-in staged negatives (stage_negatives = 1: a batch's negative
+    rows copied once per workgroup into LDS) give the bits of the same pass
+    reading every row from memory (stage_negatives = 2), under the dataflow
+    and strict schedules; and the oracle's result within the tolerance (the
+    bf16 form against its emulation)."""
+    g = gg.chung_lu(20000, 2.1, 20.0, 3)
+    p = dict(d=d, batch=128, s=s, force=force, lr0=0.02, seed=13, precision=precision)
+    Z0 = gg.init_embedding(g.n, d, 4)
+    ref = gpu_run(g, Z0, p, 2, schedule="strict", stage_negatives=2)
+    for sched in ("dataflow", "strict"):
+        got = gpu_run(g, Z0, p, 2, schedule=sched, stage_negatives=1)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), (sched, d, precision)
+    if precision == "fp32":
+        # row-wise: 1e-5, or 10x the oracle's own response to a one-ulp
+        # perturbation of the start where that is larger (at d = 2 a few rows
+        # meet a negative at close range, which amplifies any rounding)
+        exact = oracle.epoch(g, Z0, 0, oracle_params(p))
+        zp = Z0.astype(np.float64) * (1 + 2.0**-24 * np.random.default_rng(0).choice([-1.0, 1.0], size=Z0.shape))
+        row_bound = max(ROW_TOL_ONE_EPOCH, 10 * row_rel(oracle.epoch(g, zp, 0, oracle_params(p)), exact))
+        assert_parity(ref[0], exact, TOL, row_bound)
+    else:
+        emu = oracle.epoch(g, Z0, 0, oracle_params(p), emul=True)
+        same, bad = bf16_compare(ref[0], emu)
+        assert same >= 0.999 and bad == 0 and rel_fro(ref[0], emu) <= 1e-4, (same, bad)
 
 
 def test_run_twice_and_resume_bitwise():
