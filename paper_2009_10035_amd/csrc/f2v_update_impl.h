@@ -1081,15 +1081,27 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
       // repulsion from its s loss negatives
       for (int part = 0; part < 2; ++part) {
         const int64_t count = !active ? 0 : (part == 0 ? len : A.s);
+        // the row's column indices, G at a time with one load per lane group
+        // (lane l holds entry base + l), handed to the steps by lane
+        int32_t idx = -1;
+        int64_t base = -1;
         for (int64_t off = 0; __any(off < count); off += U) {
+          if (part == 0 && off - off % G != base) {
+            base = off - off % G;
+            idx = base + l < count ? A.colidx[r0 + base + l] : -1;
+          }
           int32_t v[U];
 #pragma unroll
           for (int q = 0; q < U; ++q) {
             v[q] = -1;
-            if (off + q < count) {
-              if (part == 0) {
-                v[q] = A.colidx[r0 + off + q];
-              } else {
+            if (part == 0) {
+              const int src = static_cast<int>(off - base) + q;
+              int32_t x;
+              if constexpr (G == 64) x = __builtin_amdgcn_readlane(idx, src);
+              else x = __shfl(idx, slot * G + src, 64);
+              if (off + q < count) v[q] = x;
+            } else if (off + q < count) {
+              {
                 const uint4 x = philox(static_cast<uint32_t>(u), static_cast<uint32_t>(static_cast<uint64_t>(u) >> 32),
                                        static_cast<uint32_t>(off + q), kTagEval, A.seed);
                 v[q] = uniform_index(x.x, x.y, A.n);
