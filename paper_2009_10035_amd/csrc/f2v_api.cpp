@@ -50,9 +50,11 @@ constexpr int64_t kDynamicLookahead = 4;
 // runs, later kernels of streams that share its hardware queue wait for it.
 constexpr uint32_t kMaxPolls = 1u << 20;
 // Static schedule: how long the first waves of a launch wait for the rest of
-// the grid to start before the launch switches to claiming (100 us of the
-// 100 MHz constant clock; dispatching a full grid takes a few us).
-constexpr uint32_t kArriveTicks = 10000u;
+// the grid to start before the launch switches to claiming: 1 ms of the
+// 100 MHz constant clock.  A grid that fits is placed in far less; 100 us
+// was once too short for the d = 2 kernel's first launch of a run, whose
+// switch then lowered the grid for the rest of the process.
+constexpr uint32_t kArriveTicks = 100000u;
 constexpr int64_t kMaxStatWaves = 16384;
 
 thread_local std::string g_error;
