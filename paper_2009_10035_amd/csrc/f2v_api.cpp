@@ -295,6 +295,7 @@ std::string describe_timeout(const uint32_t* e) {
                   "epoch was published)");
   return buf;
 }
+f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs* A_out, int* next_out);
 }  // namespace f2v
 
 extern "C" {
@@ -492,6 +493,33 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
       (he = f2v::launch_init_record(flag, c->at<int64_t>(L.scan_total), c->at<int64_t>(L.split_total),
                                     c->at<int64_t>(L.init_rec), s)) != hipSuccess)
     return bail(F2V_E_HIP, std::string("init kernels: ") + hipGetErrorString(he));
+  // An update kernel with a private segment (its spilled SGPRs' frame slots)
+  // makes the runtime set up scratch at its first dispatch, and that
+  // dispatch's waves can then start too slowly for the static schedule's
+  // co-residency check.  One dispatch of the static grid in which every wave
+  // exits at once (its error word, the claim counter set to 1 here and
+  // cleared by every epoch's prologue, reads nonzero) does that set-up now.
+  if (p->schedule == F2V_SCHED_DATAFLOW) {
+    hipFuncAttributes fa{};
+    if ((he = hipFuncGetAttributes(&fa, c->update_fn)) != hipSuccess)
+      return bail(F2V_E_HIP, std::string("hipFuncGetAttributes: ") + hipGetErrorString(he));
+    if (fa.localSizeBytes > 0) {
+      // the arguments of epoch 0 (every pointer valid), with the error word
+      // replaced
+      f2v::SetupArgs wsa{};
+      f2v::EpochArgs w{};
+      int wnext = 0;
+      const f2v_status wst = f2v::epoch_prepare(c, 0, &wsa, &w, &wnext);
+      if (wst != F2V_OK) return bail(wst, c->err);
+      uint32_t* tw = c->at<uint32_t>(L.ticket);
+      w.err = tw;
+      f2v::PackArgs none{};
+      void* args[] = {&w, &none};
+      if ((he = f2v::launch_fill_u32(tw, 1u, 1, s)) != hipSuccess ||
+          (he = hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s)) != hipSuccess)
+        return bail(F2V_E_HIP, std::string("update kernel set-up launch: ") + hipGetErrorString(he));
+    }
+  }
   int64_t rec[3] = {0, 0, 0};
   if ((he = hipMemcpyAsync(rec, c->at<int64_t>(L.init_rec), sizeof(rec), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (he = hipStreamSynchronize(s)) != hipSuccess)

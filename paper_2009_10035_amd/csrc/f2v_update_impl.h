@@ -48,10 +48,12 @@ struct LossShape {
   static constexpr int kStep = G * kIdxPerLane;
 };
 
-template <int G, int R, bool BF16>
+template <int G, int V, int R, bool BF16>
 struct Unroll {
-  // rows kept in flight per lane while their dot products are reduced
-  static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : (BF16 && G == 64 ? 16 : 8));
+  // rows kept in flight per lane while their dot products are reduced:
+  // sixteen only where they stay packed (bf16, two elements per lane, one row
+  // per wave)
+  static constexpr int value = R >= 4 ? 2 : (R == 2 ? 4 : (BF16 && G == 64 && V == 2 ? 16 : 8));
 };
 
 // Diagnostic counters of one wave, kept in LDS (not registers, which the
@@ -376,7 +378,7 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
                                                 float (&acc)[R][V], WaveCounters& wc) {
   constexpr int K = ListShape<G>::kIdxPerLane;
   constexpr int kStep = ListShape<G>::kStep;
-  constexpr int U = Unroll<G, R, BF16>::value < kStep ? Unroll<G, R, BF16>::value : kStep;
+  constexpr int U = Unroll<G, V, R, BF16>::value < kStep ? Unroll<G, V, R, BF16>::value : kStep;
   const int lane = slot * G + l;
   const uint64_t group_mask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (slot * G));
   const uint64_t below = (1ull << lane) - 1ull;
@@ -489,7 +491,7 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
                                                      NegStage& st, const float (&a)[R][V], float (&acc)[R][V],
                                                      WaveCounters& wc) {
   using T = typename Elem<BF16>::T;
-  constexpr int UN = Unroll<G, R, BF16>::value < 8 ? Unroll<G, R, BF16>::value : 8;
+  constexpr int UN = Unroll<G, V, R, BF16>::value < 8 ? Unroll<G, V, R, BF16>::value : 8;
   const int32_t s = A.s;
   const uint64_t hm = __ballot(has);
   if (hm == 0 || s <= 0) return;
@@ -871,10 +873,11 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
 // MULTI: a launch over several jobs (P), each on its own range of workgroups
 // with its own EpochArgs; otherwise one job (A1).
 template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI, bool STAGE = false>
-// Packed bf16 rows with one row per wave: sixteen rows in flight need more
-// registers than six waves per SIMD leave; the compiler is held to that
-// occupancy (a few values of the unit loop go to scratch).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && BF16 ? 6 : 1))) void k_update(
+// Packed bf16 rows (two elements per lane) with one row per wave: sixteen
+// rows in flight need more registers than six waves per SIMD leave; the
+// compiler is held to that occupancy.  Wider bf16 rows (four elements per
+// lane) are not held: at six waves they spilled hundreds of bytes per lane.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && BF16 && V == 2 ? 6 : 1))) void k_update(
     EpochArgs A1, PackArgs P) {
   constexpr int S = 64 / G;
   int job_block = static_cast<int>(blockIdx.x), job_blocks = static_cast<int>(gridDim.x);
@@ -983,11 +986,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
 // over its CSR neighbours (attractive part) and its s fixed loss negatives
 // (repulsive part).
 
-// Rows of a loss step: sixteen packed bf16 rows (one dword per lane) with one
-// row per wave, else eight.
-template <int G, bool BF16>
+// Rows of a loss step: sixteen packed bf16 rows (one dword of two elements
+// per lane) with one row per wave, else eight (wider rows are widened to FP32
+// on load, and sixteen of them would not fit the registers).
+template <int G, int V, bool BF16>
 struct LossRows {
-  static constexpr int value = (BF16 && G == 64) ? 16 : 8;
+  static constexpr int value = (BF16 && G == 64 && V == 2) ? 16 : 8;
 };
 
 // Row `v` (-1: none) of the loss step's batch, lane l's part: packed bf16
@@ -1034,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs A) {
   constexpr int S = 64 / G;
   constexpr int K = LossShape<G>::kIdxPerLane;
   constexpr int kStep = LossShape<G>::kStep;
-  constexpr int U = LossRows<G, BF16>::value;
+  constexpr int U = LossRows<G, V, BF16>::value;
   constexpr bool kPacked = BF16 && V == 2 && U == 16;
   const int lane = threadIdx.x & 63;
   const int slot = lane / G, l = lane % G;

@@ -27,9 +27,11 @@ def _need_gpu():
 
 
 # ("student_t", 128, 10) is the precision workload's configuration: one row
-# per wave with sixteen packed bf16 rows in flight
+# per wave with sixteen packed bf16 rows in flight; d = 256, 512 and 1024 take
+# four elements per lane, one, two and four loads per row
 @pytest.mark.parametrize("force,d,s", [("student_t", 64, 5), ("sigmoid", 128, 5), ("student_t", 2, 5),
-                                       ("sigmoid", 30, 5), ("student_t", 128, 10)])
+                                       ("sigmoid", 30, 5), ("student_t", 128, 10), ("sigmoid", 256, 5),
+                                       ("student_t", 512, 10), ("sigmoid", 1024, 5)])
 def test_bf16_matches_emulation_one_epoch(force, d, s):
     g = gg.erdos_renyi(3000, 12.0, 4)
     p = dict(d=d, batch=100, s=s, force=force, lr0=0.02, seed=21, precision="bf16")

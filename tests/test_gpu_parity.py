@@ -220,12 +220,13 @@ def test_edge_cases(case):
 
 
 @pytest.mark.parametrize("force", ["sigmoid", "student_t"])
-@pytest.mark.parametrize("d,precision", [(32, "fp32"), (128, "fp32"), (128, "bf16"), (2, "fp32")])
+@pytest.mark.parametrize("d,precision", [(32, "fp32"), (128, "fp32"), (128, "bf16"), (2, "fp32"), (256, "bf16"),
+                                         (1024, "bf16")])
 def test_loss_parity(force, d, precision):
     """Eq. 2 on the device against the oracle (the bf16 form: against the
     oracle's bf16 emulation) on a graph whose long rows (above 32 entries)
-    the loss kernel takes first; every lane-group width and the packed bf16
-    rows."""
+    the loss kernel takes first; every lane-group width, the packed bf16
+    rows and the wider bf16 rows (four elements per lane)."""
     g = gg.chung_lu(20000, 2.1, 16.0, 8)
     p = dict(d=d, batch=384, s=5, force=force, lr0=0.02, seed=12, precision=precision)
     Z0 = gg.init_embedding(g.n, d, 4)
