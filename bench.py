@@ -40,6 +40,12 @@ WORKLOADS = {
 def serve_bench(args) -> int:
     """Serving form: p50/p99 job latency and aggregate updates/s of a Poisson
     stream of jobs, admitted by HBM footprint into concurrent slots."""
+    # hardware queues: by default one per slot stream and one for torch's
+    # stream, so that a new job's copies and set-up kernels do not queue behind
+    # the update kernels of running jobs (HIP reads this when the process first
+    # uses the GPU; its own default is 4)
+    queues = args.hw_queues if args.hw_queues > 0 else args.slots + 1
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(queues, 32))
     import torch
     from paper_2009_10035_amd.serve import DeviceServer, make_job_stream, run_requests
     t0 = time.perf_counter()
@@ -80,11 +86,13 @@ def serve_bench(args) -> int:
         "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["serve"], "name": "serve", "jobs": len(jobs), "slots": args.slots,
+                   "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
                    "hbm_budget_gb": args.hbm_budget_gb, "arrival_rate_jobs_per_s": rate,
                    "closed_loop_capacity_jobs_per_s": capacity},
         "p50_s": out["p50"], "p99_s": out["p99"], "mean_s": out["mean"],
         "updates_per_s": out["updates_per_s"], "makespan_s": out["makespan"],
-        "failed": out["failed"], "retried": out["retried"], "host_seconds": out["host_seconds"],
+        "failed": out["failed"], "retried": out["retried"], "health": out["health"],
+        "host_seconds": out["host_seconds"],
         "mean_n": float(np.mean([r["n"] for r in rec])), "total_updates": out["updates"],
     }
     print(json.dumps(line), flush=True)
@@ -276,6 +284,8 @@ def main() -> int:
     ap.add_argument("--jobs", type=int, default=2000, help="serve: jobs in the stream")
     ap.add_argument("--calib-jobs", type=int, default=300, help="serve: jobs of the capacity run")
     ap.add_argument("--slots", type=int, default=16, help="serve: concurrent jobs")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="serve: HIP hardware queues of the process (default: slots + 1, at most 32)")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: HBM budget for jobs")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()

@@ -219,7 +219,12 @@ f2v_status f2v_check(f2v_ctx *ctx);
 
 /* Health record of the context (synchronises the stream): out[0] dataflow
  * launches that found their grid not co-resident and handed work out by
- * claiming instead (same results); out[1] .. out[3] reserved (0).
+ * claiming instead (same results); out[1] dependency waits of the dynamic
+ * schedule that outlasted 256 device-scope polls and went on polling with
+ * atomic read-modify-writes; out[2] those among them whose first atomic read
+ * found the awaited word already set; out[3] those that ended on the second
+ * atomic read (were the device-scope loads sometimes stale, out[2] would far
+ * exceed out[3]; by chance alone they are about equal).
  * *blocks_per_cu (may be NULL): the dataflow grid's current blocks of 256
  * threads per CU. */
 f2v_status f2v_health(f2v_ctx *ctx, uint32_t out[4], int32_t *blocks_per_cu);
@@ -368,6 +373,10 @@ f2v_status f2v_server_flush(f2v_server *s);
  * unpublished vertices of its failed epoch, as f2v_check does. */
 f2v_status f2v_server_poll(f2v_server *s, uint64_t *done, int32_t *status, int32_t cap,
                            int32_t *n_done);
+
+/* The health records (see f2v_health) of the jobs reported by
+ * f2v_server_poll so far, summed: out[0] .. out[3]. */
+f2v_status f2v_server_health(f2v_server *s, uint64_t out[4]);
 
 /* Current occupancy (any pointer may be NULL). */
 f2v_status f2v_server_query(f2v_server *s, int32_t *active, int32_t *free_slots,

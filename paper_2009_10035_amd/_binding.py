@@ -20,7 +20,7 @@ EXPORTS = (
     "f2v_vertex_trace", "f2v_footprint", "f2v_server_create", "f2v_server_submit",
     "f2v_server_flush", "f2v_server_poll", "f2v_server_query", "f2v_server_drain",
     "f2v_server_destroy", "f2v_server_last_error", "f2v_random_embedding", "f2v_health",
-    "f2v_walks", "f2v_step_size", "f2v_train_static", "f2v_selftest_publish",
+    "f2v_walks", "f2v_step_size", "f2v_train_static", "f2v_selftest_publish", "f2v_server_health",
 )
 
 STATUS = {0: "F2V_OK", 1: "F2V_E_INVALID_ARG", 2: "F2V_E_BAD_GRAPH", 3: "F2V_E_OOM", 4: "F2V_E_HIP",
@@ -113,6 +113,8 @@ def load(build_if_missing: bool = True):
     L.f2v_server_query.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     L.f2v_server_query.restype = st
+    L.f2v_server_health.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
+    L.f2v_server_health.restype = st
     L.f2v_random_embedding.argtypes = [P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, P]
     L.f2v_random_embedding.restype = st
     L.f2v_walks.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, P, P, P]

@@ -284,16 +284,24 @@ float epoch_lr(const f2v_params& p, int32_t e) {
 namespace f2v {
 // Message for a device error record (see kErrWords).
 std::string describe_timeout(const uint32_t* e) {
+  std::string m = "a device dependency wait exceeded its bound (";
+  if (e[0] & kErrWordWait) m += "a wait for a vertex's publication";
+  if ((e[0] & kErrWordWait) && (e[0] & kErrFlagWait)) m += ", ";
+  if (e[0] & kErrFlagWait) m += "a wait for a split row's early sum";
+  m += ")";
   char buf[480];
+  if (e[5] != 0) {
+    std::snprintf(buf, sizeof(buf), "; the first gave up on the early sum of row %u, whose flag then read %u",
+                  e[5] - 1, e[6]);
+    m += buf;
+  }
   if (e[1] != 0)
     std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound: %u vertices were never published in that epoch; "
-                  "the earliest is vertex %u of batch %u (word 0x%08x)", e[1], e[3], e[2], e[4]);
+                  "; %u vertices were never published in that epoch, the earliest vertex %u of batch %u (word 0x%08x)",
+                  e[1], e[3], e[2], e[4]);
   else
-    std::snprintf(buf, sizeof(buf),
-                  "a device dependency wait exceeded its bound (after the waits stopped, every vertex of the "
-                  "epoch was published)");
-  return buf;
+    std::snprintf(buf, sizeof(buf), "; after the waits stopped, every vertex of the epoch was published");
+  return m + buf;
 }
 f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs* A_out, int* next_out);
 }  // namespace f2v
@@ -406,6 +414,8 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
   const bool full = p->d == c->var->g * c->var->v * c->var->r;
   if (p->stage_negatives != 0)
     c->update_fn = f2v::find_staged(c->var, fam, full);
+  else if (p->schedule == F2V_SCHED_DYNAMIC)
+    c->update_fn = full ? c->var->dynamic_full[fam] : c->var->dynamic[fam];
   else
     c->update_fn = full ? c->var->update_full[fam] : c->var->update[fam];
   const bool bf16 = p->precision == F2V_BF16;
@@ -978,6 +988,7 @@ namespace f2v {
 void ctx_set_record_events(f2v_ctx* c, bool on) { c->record_events = on; }
 hipStream_t ctx_stream(const f2v_ctx* c) { return c->stream; }
 uint32_t* ctx_err_word(f2v_ctx* c) { return c->at<uint32_t>(c->L.err); }
+const uint32_t* ctx_health_words(const f2v_ctx* c) { return c->at<uint32_t>(c->L.health); }
 const uint32_t* ctx_vertex_words(const f2v_ctx* c) { return c->at<uint32_t>(c->L.word); }
 int64_t ctx_n(const f2v_ctx* c) { return c->p.n; }
 // The multi-job update instance of the context's kernel, and its dynamic grid.

@@ -85,6 +85,11 @@ __device__ __forceinline__ uint32_t ld_coherent_u32(const uint32_t* p) {
 __device__ __forceinline__ uint64_t ld_coherent_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// An atomic read-modify-write that changes nothing: the value as the device's
+// atomics see it.
+__device__ __forceinline__ uint32_t rmw_read_u32(const uint32_t* p) {
+  return __hip_atomic_fetch_or(const_cast<uint32_t*>(p), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void st_coherent_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

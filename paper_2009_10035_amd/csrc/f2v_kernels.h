@@ -10,19 +10,31 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
-// Device error record of a context: word 0 has bit 0 set once a dependency
-// wait exceeded its bound.  Later epochs then do nothing (the update and the
+// Device error record of a context: word 0 has bit 0 set once a wait for a
+// vertex's publication exceeded its bound, bit 1 once a late unit's wait for
+// its row's early sum did.  Later epochs then do nothing (the update and the
 // partition kernels return at once), so the vertex words of the epoch that
 // failed are kept, and a post-mortem fills [1] the number of vertices never
 // published in it, [2] the earliest batch among them, [3] one such vertex of
-// that batch and [4] its word.
-constexpr int kErrWords = 5;
+// that batch and [4] its word.  The first wave to give up on an early sum
+// names it: [5] 1 + the split row whose flag it polled, [6] that flag as an
+// atomic read sees it at the give-up.
+constexpr int kErrWords = 7;
+constexpr uint32_t kErrWordWait = 1u;
+constexpr uint32_t kErrFlagWait = 2u;
 
 // Health counters of a context (never reset by epochs; zeroed at init):
 // [0] launches of the static schedule that found the grid not co-resident and
-// switched to claiming; [1] .. [3] unused (0).
+// switched to claiming; [1] dependency waits that polled past kPlainPolls
+// device-scope loads and went on with atomic reads; [2] those among them whose
+// first atomic read found the word already set; [3] those that ended on the
+// second atomic read.  Were the loads sometimes stale, [2] would far exceed
+// [3]; by chance alone the two are about equal.
 constexpr int kHealthWords = 4;
 constexpr int kHealthFallback = 0;
+constexpr int kHealthLongWait = 1;
+constexpr int kHealthStaleRead = 2;
+constexpr int kHealthSecondRead = 3;
 
 // Claim counter (word 0) and arrival word (word kClaimStride) of an epoch's
 // update launch, each in its own 128-byte line; reset by the prologue.
@@ -120,7 +132,9 @@ struct EpochArgs {
   int32_t fan_in;           // fan-in of the combining tree of split rows
   int32_t late_window;      // batches before a unit's own whose rows are taken last
   int32_t hold;             // >= 0: this vertex's row is written but never published (a
-                            // host-forced stall, to exercise the wait bound); -1: none
+                            // host-forced stall, to exercise the wait bounds); in the
+                            // dynamic-schedule instances, a split row's early sum is not
+                            // flagged either; -1: none
   int32_t relaxed;          // 1: no waits for rows of earlier batches (zc == zn, updated
                             // in place: the asynchronous variant); 0: synchronous
   int32_t stage;            // staged-negatives instances: 1 copy the batch's negative rows
@@ -212,6 +226,8 @@ struct Variant {
   const void* update_full[3];  // the same for d = g * v * r (no lane past the row's end)
   const void* pack[3];         // the multi-job instances (their jobs' EpochArgs from PackArgs)
   const void* pack_full[3];
+  const void* dynamic[3];      // single-job instances for the dynamic schedule (the server's
+  const void* dynamic_full[3]; // jobs): their long waits go on with atomic reads
   const void* loss;            // __global__ void(LossArgs)
 };
 
@@ -268,8 +284,9 @@ hipError_t launch_walks(const int64_t* rowptr, const int32_t* colidx, int64_t n,
                         uint32_t epoch, int32_t* list, int32_t* len, hipStream_t st);
 // Completion record of a server job: the post-mortem if the job failed (see
 // kErrWords), then the job's device error record into host-visible memory
-// rec[1 .. kErrWords] and `seq` into rec[0] (written last).
-hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n,
-                         hipStream_t st);
+// rec[1 .. kErrWords], its health counters (kHealthWords) after them, and
+// `seq` into rec[0] (written last).
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* health,
+                         const uint32_t* word, int64_t n, hipStream_t st);
 
 }  // namespace f2v

@@ -699,7 +699,8 @@ __global__ void k_postmortem(const uint32_t* word, int64_t n, uint32_t* err) {
   postmortem(word, n, err);
 }
 
-__global__ void k_signal(uint32_t* rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n) {
+__global__ void k_signal(uint32_t* rec, uint32_t seq, uint32_t* err, const uint32_t* health, const uint32_t* word,
+                         int64_t n) {
   if (err[0] != 0u) {
     postmortem(word, n, err);
     __syncthreads();
@@ -707,6 +708,10 @@ __global__ void k_signal(uint32_t* rec, uint32_t seq, uint32_t* err, const uint3
   if (threadIdx.x == 0) {
     for (int i = 0; i < kErrWords; ++i)
       __hip_atomic_store(rec + 1 + i, err[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (int i = 0; i < kHealthWords; ++i)
+      __hip_atomic_store(rec + 1 + kErrWords + i, __hip_atomic_load(health + i, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(rec, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
@@ -925,9 +930,9 @@ hipError_t launch_copy_f32(float* dst, const float* src, int64_t count, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* word, int64_t n,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_signal, dim3(1), dim3(256), 0, st, host_rec, seq, err, word, n);
+hipError_t launch_signal(uint32_t* host_rec, uint32_t seq, uint32_t* err, const uint32_t* health,
+                         const uint32_t* word, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_signal, dim3(1), dim3(256), 0, st, host_rec, seq, err, health, word, n);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ namespace f2v {
 void ctx_set_record_events(f2v_ctx* c, bool on);
 hipStream_t ctx_stream(const f2v_ctx* c);
 uint32_t* ctx_err_word(f2v_ctx* c);
+const uint32_t* ctx_health_words(const f2v_ctx* c);
 const uint32_t* ctx_vertex_words(const f2v_ctx* c);
 int64_t ctx_n(const f2v_ctx* c);
 const void* ctx_pack_fn(const f2v_ctx* c);
@@ -47,7 +48,7 @@ namespace {
 // Words per slot of the completion records: the sequence number, then the
 // job's device error record.
 constexpr size_t kRecWords = 16;
-static_assert(1 + f2v::kErrWords <= kRecWords, "completion record too small");
+static_assert(1 + f2v::kErrWords + f2v::kHealthWords <= kRecWords, "completion record too small");
 
 struct Job {
   uint64_t id = 0;
@@ -100,6 +101,7 @@ struct f2v_server {
   std::vector<TableBuf> tables;
   uint64_t next_id = 1;
   uint32_t next_seq = 1;
+  uint64_t health[f2v::kHealthWords] = {};  // summed over the jobs reported so far
   std::string err;
 };
 
@@ -125,7 +127,7 @@ f2v_status enqueue_run(f2v_server* s, Job& j) {
   f2v_status st = f2v_sync_embedding(j.ctx);
   if (st != F2V_OK) return sfail(s, st, std::string("sync: ") + f2v_last_error(j.ctx));
   SRV_HIP(s, f2v::launch_signal(s->host_rec + kRecWords * j.slot, j.seq, f2v::ctx_err_word(j.ctx),
-                                f2v::ctx_vertex_words(j.ctx), f2v::ctx_n(j.ctx), s->streams[j.slot]));
+                                f2v::ctx_health_words(j.ctx), f2v::ctx_vertex_words(j.ctx), f2v::ctx_n(j.ctx), s->streams[j.slot]));
   return F2V_OK;
 }
 
@@ -277,7 +279,7 @@ f2v_status run_pack(f2v_server* s, const std::vector<uint64_t>& ids) {
       Job& j = s->jobs.at(id);
       check(f2v::ctx_sync_embedding_on(j.ctx, origin), "sync");
       check(f2v::launch_signal(s->host_rec + kRecWords * j.slot, j.seq, f2v::ctx_err_word(j.ctx),
-                               f2v::ctx_vertex_words(j.ctx), f2v::ctx_n(j.ctx), origin),
+                               f2v::ctx_health_words(j.ctx), f2v::ctx_vertex_words(j.ctx), f2v::ctx_n(j.ctx), origin),
             "signal");
     }
   }
@@ -457,6 +459,8 @@ f2v_status f2v_server_poll(f2v_server* s, uint64_t* done, int32_t* status, int32
     uint32_t rec[f2v::kErrWords];
     for (int i = 0; i < f2v::kErrWords; ++i)
       rec[i] = __atomic_load_n(s->host_rec + kRecWords * slot + 1 + i, __ATOMIC_RELAXED);
+    for (int i = 0; i < f2v::kHealthWords; ++i)
+      s->health[i] += __atomic_load_n(s->host_rec + kRecWords * slot + 1 + f2v::kErrWords + i, __ATOMIC_RELAXED);
     done[*n_done] = id;
     status[*n_done] = rec[0] != 0 ? F2V_E_TIMEOUT : F2V_OK;
     if (rec[0] != 0) s->err = "job " + std::to_string(id) + ": " + f2v::describe_timeout(rec);
@@ -465,6 +469,12 @@ f2v_status f2v_server_poll(f2v_server* s, uint64_t* done, int32_t* status, int32
     s->jobs.erase(id);
   }
   collect_graphs(s);
+  return F2V_OK;
+}
+
+f2v_status f2v_server_health(f2v_server* s, uint64_t out[4]) {
+  if (!s || !out) return F2V_E_INVALID_ARG;
+  for (int i = 0; i < 4; ++i) out[i] = i < f2v::kHealthWords ? s->health[i] : 0;
   return F2V_OK;
 }
 

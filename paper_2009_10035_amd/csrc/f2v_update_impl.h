@@ -64,6 +64,14 @@ struct WaveCounters {
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
+// A wait polls with device-scope loads.  One that is still waiting after
+// kPlainPolls of them (far beyond the usual few dozen) polls with atomic
+// read-modify-writes from then on, which act where the word itself lives and
+// so cannot return a stale copy; the health record counts such waits, those
+// whose first atomic read found the word already set, and (for comparison)
+// those that ended on the second.
+constexpr uint32_t kPlainPolls = 256;
+
 // Sleep between polls: back off from 64 to 1024 cycles.
 __device__ __forceinline__ void poll_backoff(uint32_t polls) {
   if (polls < 8) __builtin_amdgcn_s_sleep(1);
@@ -75,10 +83,10 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
 // Bounded by a count of polls (A.max_polls; a suspended wave does not poll,
 // so a suspension cannot trip it): at the bound it raises the error word,
 // which makes every other waiter stop within 64 polls.  It also stops once
-// another wave has raised it.  (The give-up block is kept to one atomic:
-// anything that names the awaited entry there keeps the entry arrays live
-// through the loop and costs the update kernel about 12% more instructions.)
-template <int U>
+// another wave has raised it.  (The give-up is kept to one atomic: naming
+// the awaited entry there costs the hot kernels registers, scratch and about
+// 10% more instructions.)
+template <int U, bool ROBUST>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
   bool any = false;
@@ -90,22 +98,30 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
 #pragma clang loop unroll(disable)
   while (true) {
     // each lane polls only its first pending entry, and the next one only if
-    // that one is published: few loads per round while many waves wait
+    // that one is published: few loads per round while many waves wait.
+    // After kPlainPolls rounds the polls become atomic reads (see there).
+    const bool rmw = ROBUST && polls >= kPlainPolls;
     any = false;
     bool polled = false;
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       if (pend[q] && !polled) {
-        pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
+        const uint32_t w = rmw ? rmw_read_u32(A.word + vid[q]) : ld_coherent_u32(A.word + vid[q]);
+        pend[q] = (w & kPublished) == 0u;
         polled = pend[q];
       }
       any |= pend[q];
     }
-    if (!__any(any)) break;
+    if (!__any(any)) {
+      if (ROBUST && (polls == kPlainPolls || polls == kPlainPolls + 1) && (threadIdx.x & 63) == 0)
+        atomicAdd(A.health + (polls == kPlainPolls ? kHealthStaleRead : kHealthSecondRead), 1u);
+      break;
+    }
+    if (ROBUST && polls == kPlainPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
     ++polls;
     if ((polls & 63u) == 0) {
       if (polls >= A.max_polls) {
-        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, kErrWordWait);
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
@@ -245,7 +261,7 @@ __device__ __forceinline__ void batch_coefs(const EpochArgs& A, const float (&dq
 // of a step: rows of the epoch-start buffer (kNext false: plain loads, no
 // wait) or of earlier batches (kNext: awaited, device-scope loads).  Adds each
 // entry's force on the group's row `a` into acc, in entry order.
-template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool kNext, int U>
+template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool kNext, int U, bool ROBUST>
 __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint32_t* ent, int cnt, bool wait,
                                                  int l, const float (&a)[R][V], float (&acc)[R][V],
                                                  WaveCounters& wc) {
@@ -263,7 +279,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait) wait_published<U>(A, vid, pend, wc);
+  if (kNext && wait) wait_published<U, ROBUST>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -370,7 +386,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
 // entries read from the epoch-start buffer are accumulated first and those of
 // earlier batches (which may need a wait) after them, each part in list order.
 // The order depends only on the list and the partition, never on timing.
-template <int G, int V, int R, bool BF16, bool FULL, int kForce>
+template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool ROBUST>
 __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active, const int32_t* nbr,
                                                 int32_t len, const int32_t* neg, int32_t nneg,
                                                 int32_t k, bool wait, int l, int slot,
@@ -446,9 +462,9 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
     // region 0: rows of the epoch-start buffer (no wait); region 1: rows of
     // earlier batches, each awaited just before it is loaded
     for (int jb = 0; __any(jb < ncur); jb += U)
-      accumulate_batch<G, V, R, BF16, FULL, kForce, false, U>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, false, U, ROBUST>(A, my_order + jb, ncur - jb, wait, l, a, acc, wc);
     for (int jb = 0; __any(jb < nnext); jb += U)
-      accumulate_batch<G, V, R, BF16, FULL, kForce, true, U>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
+      accumulate_batch<G, V, R, BF16, FULL, kForce, true, U, ROBUST>(A, my_order + ncur + jb, nnext - jb, wait, l, a, acc, wc);
     // the next step overwrites the order: every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -486,7 +502,7 @@ __device__ __forceinline__ uint32_t lds_tag(const uint32_t* t) {
 // unit takes the step (`has`); every such unit of the wave belongs to the same
 // batch k.  Entries in order j = 0 .. s-1, in chunks of UN rows; from LDS
 // (A.stage = 1) or from memory.
-template <int G, int V, int R, bool BF16, bool FULL, int kForce>
+template <int G, int V, int R, bool BF16, bool FULL, int kForce, bool ROBUST>
 __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool has, int32_t k, bool wait, int l,
                                                      NegStage& st, const float (&a)[R][V], float (&acc)[R][V],
                                                      WaveCounters& wc) {
@@ -555,7 +571,7 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
           pend[q] = wait && nxt[q] && (wd & kPublished) == 0u;
         }
       }
-      if (wait) wait_published<UN>(A, vid, pend, wc);
+      if (wait) wait_published<UN, ROBUST>(A, vid, pend, wc);
 #pragma unroll
       for (int q = 0; q < UN; ++q) {
         if (vid[q] >= 0) {
@@ -613,20 +629,29 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
 }
 
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
-// the early sum of a split row.  Bounded like wait_published.
-__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, WaveCounters& wc) {
+// the early sum of split row `u`.  Bounded like wait_published.
+template <bool ROBUST>
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
   uint32_t polls = 0;
+  bool gave_up = false;
 #pragma clang loop unroll(disable)
   while (true) {
-    if (pend) pend = ld_coherent_u32(flag) == 0u;
-    if (!__any(pend)) break;
+    const bool rmw = ROBUST && polls >= kPlainPolls;
+    if (pend) pend = (rmw ? rmw_read_u32(flag) : ld_coherent_u32(flag)) == 0u;
+    if (!__any(pend)) {
+      if (ROBUST && (polls == kPlainPolls || polls == kPlainPolls + 1) && (threadIdx.x & 63) == 0)
+        atomicAdd(A.health + (polls == kPlainPolls ? kHealthStaleRead : kHealthSecondRead), 1u);
+      break;
+    }
+    if (ROBUST && polls == kPlainPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
     ++polls;
     if ((polls & 63u) == 0) {
       if (polls >= A.max_polls) {
-        if ((threadIdx.x & 63) == 0) atomicOr(A.err, 1u);
+        if ((threadIdx.x & 63) == 0) atomicOr(A.err, kErrFlagWait);
+        gave_up = true;
         break;
       }
       if (ld_coherent_u32(A.err) != 0) break;
@@ -634,6 +659,14 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
     poll_backoff(polls);
   }
   compiler_fence();
+  if (ROBUST && gave_up) {
+    // the row of the lowest lane still waiting, and its flag as an atomic
+    // read sees it now
+    const uint64_t m = __ballot(pend);
+    if (m != 0 && static_cast<uint64_t>(threadIdx.x & 63) == static_cast<uint64_t>(__builtin_ctzll(m)) &&
+        atomicCAS(A.err + 5, 0u, static_cast<uint32_t>(u) + 1u) == 0u)
+      st_coherent_u32(A.err + 6, ld_coherent_u32(flag));
+  }
   if (A.wave_stats) {
     wc.wait += clock64() - t0;
     wc.polls += polls;
@@ -654,7 +687,7 @@ __device__ __forceinline__ void store_partial(float* row, int d, int l, const fl
 // One work unit (see the unit kinds): accumulate its list, then either take
 // the step of Eq. 10 and publish the row (whole and late units) or add the
 // partial sum into the row's combining tree (early units).
-template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool STAGE = false>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool ROBUST, bool STAGE = false>
 __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, int l, int slot,
                                              bool wait, uint32_t* order, WaveCounters& wc,
                                              NegStage* stage = nullptr) {
@@ -698,7 +731,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag(A, has_early ? A.hub_cnt + base : nullptr, wc);
+    wait_flag<ROBUST>(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
@@ -717,11 +750,11 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
                         (active ? w.beg : 0);
   const int32_t* negs = A.negs + static_cast<int64_t>(active ? w.k : 0) * A.s;
   if constexpr (STAGE) {
-    accumulate_negatives<G, V, R, BF16, FULL, FAM>(A, active && !early, w.k, wait, l, *stage, a, acc, wc);
-    accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, nullptr, 0, w.k, wait, l, slot, order, a, acc,
+    accumulate_negatives<G, V, R, BF16, FULL, FAM, ROBUST>(A, active && !early, w.k, wait, l, *stage, a, acc, wc);
+    accumulate_unit<G, V, R, BF16, FULL, FAM, ROBUST>(A, active, list, w.len, nullptr, 0, w.k, wait, l, slot, order, a, acc,
                                               wc);
   } else {
-    accumulate_unit<G, V, R, BF16, FULL, FAM>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a, acc,
+    accumulate_unit<G, V, R, BF16, FULL, FAM, ROBUST>(A, active, list, w.len, negs, nneg, w.k, wait, l, slot, order, a, acc,
                                               wc);
   }
 
@@ -801,7 +834,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       count = pcount;
       off = poff;
     }
-    if (flag_it && l == 0) st_coherent_u32(A.hub_cnt + base, 1u);
+    if (flag_it && l == 0 && !(ROBUST && u == A.hold)) st_coherent_u32(A.hub_cnt + base, 1u);
     if (A.wave_stats) wc.combine += clock64() - tc;
   }
 
@@ -872,7 +905,7 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
 
 // MULTI: a launch over several jobs (P), each on its own range of workgroups
 // with its own EpochArgs; otherwise one job (A1).
-template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI, bool STAGE = false>
+template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI, bool STAGE = false, bool ROBUST = MULTI>
 // Packed bf16 rows (two elements per lane) with one row per wave: sixteen
 // rows in flight need more registers than six waves per SIMD leave; the
 // compiler is held to that occupancy.  Wider bf16 rows (four elements per
@@ -960,9 +993,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
     if (gn < gend) nxt = A.units[static_cast<int64_t>(gn) * S + slot];
     const int gnn = __builtin_amdgcn_readfirstlane(gn < gend ? following(gn) : gend);
     if constexpr (STAGE) {
-      process_unit<G, V, R, BF16, FULL, FAM, true>(A, cur, l, slot, wait, order, wc, &stage_lds);
+      process_unit<G, V, R, BF16, FULL, FAM, ROBUST, true>(A, cur, l, slot, wait, order, wc, &stage_lds);
     } else {
-      process_unit<G, V, R, BF16, FULL, FAM>(A, cur, l, slot, wait, order, wc);
+      process_unit<G, V, R, BF16, FULL, FAM, ROBUST>(A, cur, l, slot, wait, order, wc);
     }
     cur = nxt;
     g = gn;

@@ -3,13 +3,14 @@
 
 namespace f2v {
 
-#define F2V_UPDATE(G, V, R, B, FULL, M) \
-  {reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 0, M>), \
-   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 1, M>), \
-   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 2, M>)}
+#define F2V_UPDATE(G, V, R, B, FULL, M, ROB) \
+  {reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 0, M, false, ROB>), \
+   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 1, M, false, ROB>), \
+   reinterpret_cast<const void*>(&k_update<G, V, R, B, FULL, 2, M, false, ROB>)}
 #define F2V_VARIANT(G, V, R, B) \
-  Variant{G, V, R, B, F2V_UPDATE(G, V, R, B, false, false), F2V_UPDATE(G, V, R, B, true, false), \
-          F2V_UPDATE(G, V, R, B, false, true), F2V_UPDATE(G, V, R, B, true, true), \
+  Variant{G, V, R, B, F2V_UPDATE(G, V, R, B, false, false, false), F2V_UPDATE(G, V, R, B, true, false, false), \
+          F2V_UPDATE(G, V, R, B, false, true, true), F2V_UPDATE(G, V, R, B, true, true, true), \
+          F2V_UPDATE(G, V, R, B, false, false, true), F2V_UPDATE(G, V, R, B, true, false, true), \
           reinterpret_cast<const void*>(&k_loss<G, V, R, B>)}
 
 extern const Variant kVariants_f32_v1[] = {

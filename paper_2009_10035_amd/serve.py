@@ -158,6 +158,13 @@ class DeviceServer:
     def last_error(self) -> str:
         return self.lib.f2v_server_last_error(self.handle).decode(errors="replace")
 
+    def health(self) -> dict:
+        """Health counters summed over the jobs reported so far (f2v_health)."""
+        out = (ctypes.c_uint64 * 4)()
+        check(self.lib.f2v_server_health(self.handle, out))
+        return {"fallbacks": int(out[0]), "long_waits": int(out[1]), "first_atomic_read": int(out[2]),
+                "second_atomic_read": int(out[3])}
+
     def release(self, jid: int) -> None:
         self.buffers.pop(jid, None)
 
@@ -221,6 +228,9 @@ class SimulatedServer:
 
     def last_error(self) -> str:
         return ""
+
+    def health(self) -> dict:
+        return {"fallbacks": 0, "long_waits": 0, "first_atomic_read": 0, "second_atomic_read": 0}
 
     def release(self, jid) -> None:
         pass
@@ -306,4 +316,4 @@ def run_requests(jobs, server, *, clock=time.perf_counter, sleep=time.sleep, pac
                 p99=float(np.percentile(lat, 99)) if len(lat) else 0.0,
                 mean=float(lat.mean()) if len(lat) else 0.0, makespan=makespan,
                 updates=total_updates, updates_per_s=total_updates / makespan if makespan > 0 else 0.0,
-                host_seconds=dict(host), records=records, results=results)
+                host_seconds=dict(host), health=server.health(), records=records, results=results)

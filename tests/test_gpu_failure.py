@@ -49,7 +49,37 @@ def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
     assert ei.value.name == "F2V_E_TIMEOUT"
     msg = str(ei.value)
     assert "1 vertices were never published" in msg and f"vertex {v} of batch 0" in msg, msg
+    # the kind of wait that gave up
+    assert "a wait for a vertex's publication" in msg and "early sum" not in msg, msg
     tr.check()    # the error was reported once
+    h = tr.health()
+    if schedule == "dynamic":
+        # the waits for the held vertex went on with atomic reads, which found
+        # it unpublished too
+        assert h["long_waits"] >= 1 and h["first_atomic_read"] == 0 and h["second_atomic_read"] == 0, h
+    else:
+        assert h["long_waits"] == 0 and h["first_atomic_read"] == 0, h
+    tr.close()
+
+
+def test_withheld_early_sum_times_out_and_is_named(monkeypatch):
+    # chunk 4: the vertex at position 0 (degree about 12) is a split row, whose
+    # late unit waits for the flag of its early sum; the hold keeps that flag
+    # (and the vertex's word) unset in the dynamic schedule's kernels
+    g, p, v = held_case()
+    assert g.rowptr[v + 1] - g.rowptr[v] > 4
+    monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
+    monkeypatch.setenv("F2V_WAIT_POLLS", "4096")
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(gg.init_embedding(g.n, p["d"], 3), dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p, total_epochs=3, schedule="dynamic", chunk=4))
+    tr.epoch(0)
+    with pytest.raises(F2VError) as ei:
+        tr.check()
+    msg = str(ei.value)
+    assert ei.value.name == "F2V_E_TIMEOUT"
+    assert "a wait for a split row's early sum" in msg, msg
+    assert f"gave up on the early sum of row {v}, whose flag then read 0" in msg, msg
     tr.close()
 
 
