@@ -493,6 +493,7 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
   if ((he = f2v::launch_fill_u32(flag, 0u, 1, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(errw, 0u, f2v::kErrWords, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(c->at<uint32_t>(L.health), 0u, f2v::kHealthWords, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, L.hub_slot_cap, s)) != hipSuccess ||
       (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
       (he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
@@ -675,8 +676,6 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;
-  sa.hub_cnt = c->at<uint32_t>(L.hub_cnt);
-  sa.hub_total = c->hub_total;
 
   EpochArgs& A = *A_out;
   A = EpochArgs{};
@@ -844,7 +843,10 @@ f2v_status f2v_check(f2v_ctx* c) {
     }
   }
   if (e[0] != 0) {
+    // after a give-up the waits stopped early: a flag may have been cleared by
+    // its reader before its tree set it, so the trees start over from zeros
     HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, f2v::kErrWords, c->stream));
+    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.hub_cnt), 0u, c->L.hub_slot_cap, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return fail(&c->err, F2V_E_TIMEOUT, f2v::describe_timeout(e));
   }

@@ -110,7 +110,9 @@ struct EpochArgs {
   const int32_t* ngroups;   // device scalar: ticket groups this epoch
   const int64_t* hub_base;  // vertex -> first node of its combining tree (split rows)
   uint32_t* hub_cnt;        // tree node -> arrival counter; a row's first slot flags its
-                            // early sum (all zero at the start of an epoch)
+                            // early sum.  Zeroed at init; the kernel clears each counter
+                            // once its node is complete and each flag once it is read,
+                            // so every epoch starts from zeros
   float* hub_part;          // tree node -> partial sum [d]
   uint32_t* err;            // device error record [kErrWords] (word 0 bit 0: a wait exceeded its bound)
   uint32_t* health;         // health counters [kHealthWords]
@@ -194,8 +196,6 @@ struct SetupArgs {
   int32_t feistel_half;
   uint32_t feistel_mask;
   const uint32_t* err;      // the context's error record: set = do nothing (k_walks: may be nullptr)
-  uint32_t* hub_cnt;        // tree counters and early-sum flags, reset every epoch
-  int64_t hub_total;        // their number
 };
 
 struct LossArgs {

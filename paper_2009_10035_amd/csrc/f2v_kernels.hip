@@ -775,16 +775,6 @@ __global__ __launch_bounds__(64) void k_selftest_publish(float* rows, uint32_t* 
   if (!writer && lane == 0) atomicAdd(out + 2, 1u);
 }
 
-// Tree counters and early-sum flags of split rows start every epoch at zero
-// (device-scope stores: they are next used by device-scope atomics and polls).
-template <bool MULTI>
-__global__ void k_reset_hub(SetupArgs A1, const SetupArgs* tab) {
-  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < A.hub_total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    st_coherent_u32(A.hub_cnt + i, 0u);
-}
-
 int grid_for(int64_t work, int threads) {
   int64_t g = (work + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -798,8 +788,7 @@ int grid_for(int64_t work, int threads) {
 // value, the multi-job ones from the table (blockIdx.y = job).
 template <bool MULTI>
 void launch_prologue(const SetupArgs& one, const SetupArgs* d_tab, unsigned y, int64_t positions, int64_t walks,
-                     int64_t splits, int64_t batches, int batch_threads, int64_t tickets, int64_t hub,
-                     hipStream_t st) {
+                     int64_t splits, int64_t batches, int batch_threads, int64_t tickets, hipStream_t st) {
   hipLaunchKernelGGL(k_setup_positions<MULTI>, dim3(grid_for(positions, 256), y), dim3(256), 0, st, one, d_tab);
   if (walks > 0) hipLaunchKernelGGL(k_walks<MULTI>, dim3(grid_for(walks, 256), y), dim3(256), 0, st, one, d_tab);
   if (splits > 0) {
@@ -811,7 +800,6 @@ void launch_prologue(const SetupArgs& one, const SetupArgs* d_tab, unsigned y, i
                      d_tab);
   hipLaunchKernelGGL(k_batch_starts<MULTI>, dim3(1, y), dim3(kScanThreads), 0, st, one, d_tab);
   hipLaunchKernelGGL(k_tickets<MULTI>, dim3(grid_for(tickets, 256), y), dim3(256), 0, st, one, d_tab);
-  if (hub > 0) hipLaunchKernelGGL(k_reset_hub<MULTI>, dim3(grid_for(hub, 256), y), dim3(256), 0, st, one, d_tab);
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
@@ -823,7 +811,7 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
 // the largest need among the jobs; the kernels stride over their own job's
 // sizes, so the surplus blocks of a smaller job find nothing to do.
 hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int njobs, hipStream_t st) {
-  int64_t positions = 0, walks = 0, splits = 0, batches = 0, tickets = 0, hub = 0;
+  int64_t positions = 0, walks = 0, splits = 0, batches = 0, tickets = 0;
   int batch_threads = 256;
   for (int j = 0; j < njobs; ++j) {
     const SetupArgs& a = h_tab[j];
@@ -833,15 +821,14 @@ hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int
     splits = std::max(splits, a.nsplit);
     batches = std::max(batches, static_cast<int64_t>(a.nb));
     tickets = std::max(tickets, a.n + 2 * static_cast<int64_t>(a.nb) * a.slots);
-    hub = std::max(hub, a.hub_total);
     if (a.b >= 1024) batch_threads = 1024;
   }
   const SetupArgs one = d_tab ? SetupArgs{} : h_tab[0];
   const unsigned y = static_cast<unsigned>(njobs);
   if (d_tab) {
-    launch_prologue<true>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, hub, st);
+    launch_prologue<true>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, st);
   } else {
-    launch_prologue<false>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, hub, st);
+    launch_prologue<false>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, st);
   }
   return hipGetLastError();
 }

@@ -739,6 +739,8 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
         const int e0 = (r * G + l) * V;
         if ((FULL || e0 < A.d)) load_coherent<V, false>(root + e0, acc[r]);
       }
+      // the flag's only reader clears it for the next epoch
+      if (l == 0) st_coherent_u32(A.hub_cnt + base, 0u);
     }
   }
 
@@ -787,6 +789,9 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       old = __shfl(old, slot * G, 64);
       compiler_fence();
       const bool last = climbing && old + 1u == static_cast<uint32_t>(nchild);
+      // every child has arrived: the node's counter is clear for the next
+      // epoch (no reset kernel stands between two epochs' atomics on it)
+      if (last && l == 0) st_coherent_u32(A.hub_cnt + base + poff + parent, 0u);
       if (last) {
         // children in index order, kLoadsInFlight partial rows at a time
         const float* kids = A.hub_part + (base + off + first) * A.d;
