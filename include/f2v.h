@@ -220,11 +220,8 @@ f2v_status f2v_check(f2v_ctx *ctx);
 /* Health record of the context (synchronises the stream): out[0] dataflow
  * launches that found their grid not co-resident and handed work out by
  * claiming instead (same results); out[1] dependency waits of the dynamic
- * schedule that outlasted 256 device-scope polls and went on polling with
- * atomic read-modify-writes; out[2] those among them whose first atomic read
- * found the awaited word already set; out[3] those that ended on the second
- * atomic read (were the device-scope loads sometimes stale, out[2] would far
- * exceed out[3]; by chance alone they are about equal).
+ * schedule that polled more than 256 times (how long units wait under load);
+ * out[2], out[3] reserved (0).
  * *blocks_per_cu (may be NULL): the dataflow grid's current blocks of 256
  * threads per CU. */
 f2v_status f2v_health(f2v_ctx *ctx, uint32_t out[4], int32_t *blocks_per_cu);

@@ -110,14 +110,12 @@ class Trainer:
     def health(self):
         """Health record (see f2v_health in include/f2v.h): dict with the
         dataflow launches that fell back to claiming, the dataflow grid's
-        blocks per CU, the dynamic schedule's waits that went on with atomic
-        reads, and those that ended on the first and on the second atomic
-        read."""
+        blocks per CU, and the dynamic schedule's waits of more than 256
+        polls."""
         out = (ctypes.c_uint32 * 4)()
         bpc = ctypes.c_int32(0)
         check(self.lib.f2v_health(self.ctx, out, ctypes.byref(bpc)), self.ctx)
-        return {"fallbacks": int(out[0]), "blocks_per_cu": int(bpc.value), "long_waits": int(out[1]),
-                "first_atomic_read": int(out[2]), "second_atomic_read": int(out[3])}
+        return {"fallbacks": int(out[0]), "blocks_per_cu": int(bpc.value), "long_waits": int(out[1])}
 
     def set_diagnostics(self, enable: bool = True) -> None:
         check(self.lib.f2v_set_diagnostics(self.ctx, 1 if enable else 0), self.ctx)

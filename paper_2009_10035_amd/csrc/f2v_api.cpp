@@ -161,7 +161,7 @@ Layout layout_of(const f2v_params& p) {
   L.loss_out = take(3 * 8);
   L.wave_stats = take(size_t(kMaxStatWaves) * f2v::kWaveStats * 8);
   L.trace = take(size_t(n) * 8);
-  L.ticket = take(size_t(f2v::kTicketWords) * 4);
+  L.ticket = take(size_t(2 * f2v::kTicketWords) * 4);
   L.total = off;
   return L;
 }
@@ -235,6 +235,7 @@ struct f2v_ctx {
   float* zbuf[2] = {nullptr, nullptr};
   uint16_t* bbuf[2] = {nullptr, nullptr};
   int cur = 0;
+  int ticket_set = 0;       // which of the two claim-counter sets the next epoch uses
   const Variant* var = nullptr;
   const void* update_fn = nullptr;  // var's update kernel for this d
   int update_grid = 0;      // grid of the static (dataflow) schedule: blocks_per_cu per CU
@@ -291,8 +292,10 @@ std::string describe_timeout(const uint32_t* e) {
   m += ")";
   char buf[480];
   if (e[5] != 0) {
-    std::snprintf(buf, sizeof(buf), "; the first gave up on the early sum of row %u, whose flag then read %u",
-                  e[5] - 1, e[6]);
+    std::snprintf(buf, sizeof(buf),
+                  "; the first gave up on the early sum of row %u, whose flag then read %u (%u early units, "
+                  "first tree node's counter %u)",
+                  e[5] - 1, e[6], e[7], e[8]);
     m += buf;
   }
   if (e[1] != 0)
@@ -494,6 +497,7 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
       (he = f2v::launch_fill_u32(errw, 0u, f2v::kErrWords, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(c->at<uint32_t>(L.health), 0u, f2v::kHealthWords, s)) != hipSuccess ||
       (he = f2v::launch_fill_u32(c->at<uint32_t>(L.hub_cnt), 0u, L.hub_slot_cap, s)) != hipSuccess ||
+      (he = f2v::launch_fill_u32(c->at<uint32_t>(L.ticket), 0u, 2 * f2v::kTicketWords, s)) != hipSuccess ||
       (he = f2v::launch_check_csr(d_rowptr, d_colidx, p->n, p->nnz, flag, s)) != hipSuccess ||
       (he = f2v::launch_hub_base(d_rowptr, p->n, c->p.chunk, c->fan_in, c->at<int64_t>(L.hub_base),
                                  c->at<int64_t>(L.scan_scratch), c->at<int64_t>(L.scan_total), s)) != hipSuccess ||
@@ -508,8 +512,8 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
   // makes the runtime set up scratch at its first dispatch, and that
   // dispatch's waves can then start too slowly for the static schedule's
   // co-residency check.  One dispatch of the static grid in which every wave
-  // exits at once (its error word, the claim counter set to 1 here and
-  // cleared by every epoch's prologue, reads nonzero) does that set-up now.
+  // exits at once (its error word, a claim counter set to 1 for it and zeroed
+  // again after it, reads nonzero) does that set-up now.
   if (p->schedule == F2V_SCHED_DATAFLOW) {
     hipFuncAttributes fa{};
     if ((he = hipFuncGetAttributes(&fa, c->update_fn)) != hipSuccess)
@@ -527,7 +531,8 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
       f2v::PackArgs none{};
       void* args[] = {&w, &none};
       if ((he = f2v::launch_fill_u32(tw, 1u, 1, s)) != hipSuccess ||
-          (he = hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s)) != hipSuccess)
+          (he = hipLaunchKernel(c->update_fn, dim3(c->update_grid), dim3(kBlock), args, 0, s)) != hipSuccess ||
+          (he = f2v::launch_fill_u32(tw, 0u, 1, s)) != hipSuccess)
         return bail(F2V_E_HIP, std::string("update kernel set-up launch: ") + hipGetErrorString(he));
     }
   }
@@ -660,7 +665,7 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   sa.lstart = c->at<int32_t>(L.lstart);
   sa.units = c->at<f2v::Unit>(L.units);
   sa.ngroups = c->at<int32_t>(L.ngroups);
-  sa.ticket = c->at<uint32_t>(L.ticket);
+  sa.ticket = c->at<uint32_t>(L.ticket) + (1 - c->ticket_set) * f2v::kTicketWords;
   sa.n = p.n;
   sa.nsplit = c->nsplit;
   sa.late_window = c->late_window;
@@ -719,7 +724,7 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   A.max_polls = c->max_polls;
   A.arrive_ticks = kArriveTicks;
   A.hold = c->hold;
-  A.ticket = c->at<uint32_t>(L.ticket);
+  A.ticket = c->at<uint32_t>(L.ticket) + c->ticket_set * f2v::kTicketWords;
   A.fan_in = c->fan_in;
   A.late_window = c->late_window;
   A.wave_stats = nullptr;
@@ -731,7 +736,10 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   return F2V_OK;
 }
 
-void epoch_commit(f2v_ctx* c, int next) { c->cur = next; }
+void epoch_commit(f2v_ctx* c, int next) {
+  c->cur = next;
+  c->ticket_set = 1 - c->ticket_set;
+}
 
 }  // namespace f2v
 
@@ -844,9 +852,11 @@ f2v_status f2v_check(f2v_ctx* c) {
   }
   if (e[0] != 0) {
     // after a give-up the waits stopped early: a flag may have been cleared by
-    // its reader before its tree set it, so the trees start over from zeros
+    // its reader before its tree set it, so the trees start over from zeros;
+    // the prologues that returned at once left the claim counters as they were
     HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.err), 0u, f2v::kErrWords, c->stream));
     HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.hub_cnt), 0u, c->L.hub_slot_cap, c->stream));
+    HIP_TRY(c, f2v::launch_fill_u32(c->at<uint32_t>(c->L.ticket), 0u, 2 * f2v::kTicketWords, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return fail(&c->err, F2V_E_TIMEOUT, f2v::describe_timeout(e));
   }

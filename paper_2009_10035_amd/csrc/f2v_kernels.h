@@ -18,26 +18,26 @@ constexpr uint32_t kPublished = 0x80000000u;
 // published in it, [2] the earliest batch among them, [3] one such vertex of
 // that batch and [4] its word.  The first wave to give up on an early sum
 // names it: [5] 1 + the split row whose flag it polled, [6] that flag as an
-// atomic read sees it at the give-up.
-constexpr int kErrWords = 7;
+// atomic read sees it at the give-up, [7] the row's early-unit count and [8]
+// the arrival counter of its tree's first node above the units (0 if it has
+// one early unit).
+constexpr int kErrWords = 9;
 constexpr uint32_t kErrWordWait = 1u;
 constexpr uint32_t kErrFlagWait = 2u;
 
 // Health counters of a context (never reset by epochs; zeroed at init):
 // [0] launches of the static schedule that found the grid not co-resident and
-// switched to claiming; [1] dependency waits that polled past kPlainPolls
-// device-scope loads and went on with atomic reads; [2] those among them whose
-// first atomic read found the word already set; [3] those that ended on the
-// second atomic read.  Were the loads sometimes stale, [2] would far exceed
-// [3]; by chance alone the two are about equal.
+// switched to claiming; [1] dependency waits of the dynamic-schedule
+// instances that polled more than 256 times; [2], [3] unused (0).
 constexpr int kHealthWords = 4;
 constexpr int kHealthFallback = 0;
 constexpr int kHealthLongWait = 1;
-constexpr int kHealthStaleRead = 2;
-constexpr int kHealthSecondRead = 3;
 
 // Claim counter (word 0) and arrival word (word kClaimStride) of an epoch's
-// update launch, each in its own 128-byte line; reset by the prologue.
+// update launch, each in its own 128-byte line.  A context has two such sets
+// and its epochs take them in turn; each epoch's prologue zeroes the set the
+// next epoch will use, so no reset lands just before the atomics it clears
+// for.
 constexpr int kClaimStride = 32;
 constexpr int kTicketWords = 2 * kClaimStride;
 // Arrival word: count of waves that have started, bit 31 set once the launch
@@ -112,7 +112,8 @@ struct EpochArgs {
   uint32_t* hub_cnt;        // tree node -> arrival counter; a row's first slot flags its
                             // early sum.  Zeroed at init; the kernel clears each counter
                             // once its node is complete and each flag once it is read,
-                            // so every epoch starts from zeros
+                            // so every epoch starts from zeros.  Within a launch every
+                            // write to them is an atomic (no plain or device-scope store)
   float* hub_part;          // tree node -> partial sum [d]
   uint32_t* err;            // device error record [kErrWords] (word 0 bit 0: a wait exceeded its bound)
   uint32_t* health;         // health counters [kHealthWords]
@@ -186,7 +187,7 @@ struct SetupArgs {
   int32_t* lstart;          // [nb] first ticket of each batch's second part
   Unit* units;
   int32_t* ngroups;
-  uint32_t* ticket;         // claim counter and arrival word (reset here)
+  uint32_t* ticket;         // the next epoch's claim counter and arrival word (zeroed here)
   int64_t n, nsplit;
   int32_t b, s, nb, chunk, slots;  // slots = lane groups per wave
   int32_t late_window;      // batches before a split row's own whose neighbours go late

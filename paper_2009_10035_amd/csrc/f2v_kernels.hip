@@ -410,7 +410,7 @@ __global__ void k_batch_starts(SetupArgs A1, const SetupArgs* tab) {
     A.bstart[A.nb] = static_cast<int32_t>(carry);
     *A.ngroups = static_cast<int32_t>(carry / A.slots);
   }
-  // the claim counter and the arrival word of the update launch
+  // the claim counter and the arrival word of the next epoch's update launch
   for (int i = threadIdx.x; i < kTicketWords; i += blockDim.x) st_coherent_u32(A.ticket + i, 0u);
   __syncthreads();
   __threadfence_block();

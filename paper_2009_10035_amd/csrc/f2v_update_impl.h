@@ -64,13 +64,10 @@ struct WaveCounters {
   uint64_t last_wait_end;  // wall clock at the end of the unit's last wait
 };
 
-// A wait polls with device-scope loads.  One that is still waiting after
-// kPlainPolls of them (far beyond the usual few dozen) polls with atomic
-// read-modify-writes from then on, which act where the word itself lives and
-// so cannot return a stale copy; the health record counts such waits, those
-// whose first atomic read found the word already set, and (for comparison)
-// those that ended on the second.
-constexpr uint32_t kPlainPolls = 256;
+// Waits of the dynamic-schedule instances that poll more than kLongPolls
+// times are counted in the health record (a measure of how long units wait
+// under load; the usual wait is a few dozen polls).
+constexpr uint32_t kLongPolls = 256;
 
 // Sleep between polls: back off from 64 to 1024 cycles.
 __device__ __forceinline__ void poll_backoff(uint32_t polls) {
@@ -98,26 +95,19 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
 #pragma clang loop unroll(disable)
   while (true) {
     // each lane polls only its first pending entry, and the next one only if
-    // that one is published: few loads per round while many waves wait.
-    // After kPlainPolls rounds the polls become atomic reads (see there).
-    const bool rmw = ROBUST && polls >= kPlainPolls;
+    // that one is published: few loads per round while many waves wait
     any = false;
     bool polled = false;
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       if (pend[q] && !polled) {
-        const uint32_t w = rmw ? rmw_read_u32(A.word + vid[q]) : ld_coherent_u32(A.word + vid[q]);
-        pend[q] = (w & kPublished) == 0u;
+        pend[q] = (ld_coherent_u32(A.word + vid[q]) & kPublished) == 0u;
         polled = pend[q];
       }
       any |= pend[q];
     }
-    if (!__any(any)) {
-      if (ROBUST && (polls == kPlainPolls || polls == kPlainPolls + 1) && (threadIdx.x & 63) == 0)
-        atomicAdd(A.health + (polls == kPlainPolls ? kHealthStaleRead : kHealthSecondRead), 1u);
-      break;
-    }
-    if (ROBUST && polls == kPlainPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
+    if (!__any(any)) break;
+    if (ROBUST && polls == kLongPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
     ++polls;
     if ((polls & 63u) == 0) {
       if (polls >= A.max_polls) {
@@ -631,7 +621,8 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
 // Wait until the flag word at `flag` (per lane group; nullptr: none) is set:
 // the early sum of split row `u`.  Bounded like wait_published.
 template <bool ROBUST>
-__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, WaveCounters& wc) {
+__device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* flag, int32_t u, int32_t nch,
+                                          WaveCounters& wc) {
   bool pend = flag != nullptr;
   if (!__any(pend)) return;
   const uint64_t t0 = A.wave_stats ? clock64() : 0;
@@ -639,14 +630,9 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
   bool gave_up = false;
 #pragma clang loop unroll(disable)
   while (true) {
-    const bool rmw = ROBUST && polls >= kPlainPolls;
-    if (pend) pend = (rmw ? rmw_read_u32(flag) : ld_coherent_u32(flag)) == 0u;
-    if (!__any(pend)) {
-      if (ROBUST && (polls == kPlainPolls || polls == kPlainPolls + 1) && (threadIdx.x & 63) == 0)
-        atomicAdd(A.health + (polls == kPlainPolls ? kHealthStaleRead : kHealthSecondRead), 1u);
-      break;
-    }
-    if (ROBUST && polls == kPlainPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
+    if (pend) pend = ld_coherent_u32(flag) == 0u;
+    if (!__any(pend)) break;
+    if (ROBUST && polls == kLongPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
     ++polls;
     if ((polls & 63u) == 0) {
       if (polls >= A.max_polls) {
@@ -660,12 +646,16 @@ __device__ __forceinline__ void wait_flag(const EpochArgs& A, const uint32_t* fl
   }
   compiler_fence();
   if (ROBUST && gave_up) {
-    // the row of the lowest lane still waiting, and its flag as an atomic
-    // read sees it now
+    // the row of the lowest lane still waiting, its flag as an atomic read
+    // sees it now, its early-unit count and the arrival counter of its tree's
+    // first node above the units
     const uint64_t m = __ballot(pend);
     if (m != 0 && static_cast<uint64_t>(threadIdx.x & 63) == static_cast<uint64_t>(__builtin_ctzll(m)) &&
-        atomicCAS(A.err + 5, 0u, static_cast<uint32_t>(u) + 1u) == 0u)
-      st_coherent_u32(A.err + 6, ld_coherent_u32(flag));
+        atomicCAS(A.err + 5, 0u, static_cast<uint32_t>(u) + 1u) == 0u) {
+      st_coherent_u32(A.err + 6, rmw_read_u32(flag));
+      st_coherent_u32(A.err + 7, static_cast<uint32_t>(nch));
+      st_coherent_u32(A.err + 8, nch > 1 ? rmw_read_u32(flag + nch) : 0u);
+    }
   }
   if (A.wave_stats) {
     wc.wait += clock64() - t0;
@@ -731,7 +721,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const bool has_early = late && w.nch > 0;
   if (__any(has_early)) {
     const int64_t base = has_early ? A.hub_base[u] : 0;
-    wait_flag<ROBUST>(A, has_early ? A.hub_cnt + base : nullptr, u, wc);
+    wait_flag<ROBUST>(A, has_early ? A.hub_cnt + base : nullptr, u, w.nch, wc);
     if (has_early) {
       const float* root = A.hub_part + (base + tree_nodes(w.nch, A.fan_in) - 1) * A.d;
 #pragma unroll
@@ -740,7 +730,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
         if ((FULL || e0 < A.d)) load_coherent<V, false>(root + e0, acc[r]);
       }
       // the flag's only reader clears it for the next epoch
-      if (l == 0) st_coherent_u32(A.hub_cnt + base, 0u);
+      if (l == 0) (void)atomicExch(A.hub_cnt + base, 0u);
     }
   }
 
@@ -791,7 +781,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       const bool last = climbing && old + 1u == static_cast<uint32_t>(nchild);
       // every child has arrived: the node's counter is clear for the next
       // epoch (no reset kernel stands between two epochs' atomics on it)
-      if (last && l == 0) st_coherent_u32(A.hub_cnt + base + poff + parent, 0u);
+      if (last && l == 0) (void)atomicExch(A.hub_cnt + base + poff + parent, 0u);
       if (last) {
         // children in index order, kLoadsInFlight partial rows at a time
         const float* kids = A.hub_part + (base + off + first) * A.d;
@@ -839,7 +829,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       count = pcount;
       off = poff;
     }
-    if (flag_it && l == 0 && !(ROBUST && u == A.hold)) st_coherent_u32(A.hub_cnt + base, 1u);
+    if (flag_it && l == 0 && !(ROBUST && u == A.hold)) (void)atomicExch(A.hub_cnt + base, 1u);
     if (A.wave_stats) wc.combine += clock64() - tc;
   }
 

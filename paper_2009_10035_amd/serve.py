@@ -162,8 +162,7 @@ class DeviceServer:
         """Health counters summed over the jobs reported so far (f2v_health)."""
         out = (ctypes.c_uint64 * 4)()
         check(self.lib.f2v_server_health(self.handle, out))
-        return {"fallbacks": int(out[0]), "long_waits": int(out[1]), "first_atomic_read": int(out[2]),
-                "second_atomic_read": int(out[3])}
+        return {"fallbacks": int(out[0]), "long_waits": int(out[1])}
 
     def release(self, jid: int) -> None:
         self.buffers.pop(jid, None)
@@ -230,7 +229,7 @@ class SimulatedServer:
         return ""
 
     def health(self) -> dict:
-        return {"fallbacks": 0, "long_waits": 0, "first_atomic_read": 0, "second_atomic_read": 0}
+        return {"fallbacks": 0, "long_waits": 0}
 
     def release(self, jid) -> None:
         pass

@@ -53,12 +53,12 @@ def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
     assert "a wait for a vertex's publication" in msg and "early sum" not in msg, msg
     tr.check()    # the error was reported once
     h = tr.health()
+    # the waits for the held vertex are counted as long in the dynamic
+    # schedule's kernels (the dataflow kernels do not count)
     if schedule == "dynamic":
-        # the waits for the held vertex went on with atomic reads, which found
-        # it unpublished too
-        assert h["long_waits"] >= 1 and h["first_atomic_read"] == 0 and h["second_atomic_read"] == 0, h
+        assert h["long_waits"] >= 1, h
     else:
-        assert h["long_waits"] == 0 and h["first_atomic_read"] == 0, h
+        assert h["long_waits"] == 0, h
     tr.close()
 
 

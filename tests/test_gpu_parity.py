@@ -155,6 +155,35 @@ def test_run_twice_and_resume_bitwise():
     assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("schedule", ["dataflow", "dynamic"])
+def test_same_epoch_twice_in_a_row(schedule):
+    """One epoch number run twice in a row on one context (each launch takes
+    the claim counters the one before it zeroed, and finds the split rows'
+    tree counters and flags cleared by the one before it) equals that epoch
+    applied twice: the same bits as two fresh contexts in turn, and the
+    oracle's two applications within the FP32 bound.  Chunk 8 makes most rows
+    split rows."""
+    g = gg.chung_lu(20000, 2.1, 16.0, 9)
+    p = dict(d=32, batch=256, s=5, force="sigmoid", lr0=0.02, seed=4, chunk=8)
+    Z0 = gg.init_embedding(g.n, 32, 6)
+    rowptr, colidx = device_graph(g)
+    z = torch.from_numpy(np.ascontiguousarray(Z0, dtype=np.float32)).cuda()
+    tr = f2v.Trainer(rowptr, colidx, z, lib_params(g, p, schedule=schedule, chunk=8))
+    tr.epoch(2)
+    tr.epoch(2)
+    tr.sync_embedding()
+    tr.check()
+    got = z.cpu().numpy().copy()
+    tr.close()
+    once = gpu_run(g, Z0, p, 1, first=2, snapshots=False, schedule=schedule, chunk=8)[-1]
+    twice = gpu_run(g, once, p, 1, first=2, snapshots=False, schedule=schedule, chunk=8)[-1]
+    assert np.array_equal(got, twice)
+    q = oracle_params(p)
+    ref = oracle.epoch(g, oracle.epoch(g, Z0, 2, q), 2, q)
+    # two epochs of trajectory: the free-running bounds
+    assert rel_fro(got, ref) <= TOL and row_rel(got, ref) <= ROW_TOL_FREE
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 16, 24, 64, 100, 128, 192, 256, 512, 1024])
 @pytest.mark.parametrize("force", ["sigmoid", "student_t"])
 def test_dimensions(d, force):
