@@ -241,7 +241,9 @@ struct f2v_ctx {
   int update_grid = 0;      // grid of the static (dataflow) schedule: blocks_per_cu per CU
   int dev = 0;              // device the context runs on
   int blocks_per_cu = 0;    // the occupancy limit, less one for every launch found not co-resident
-  int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit or the job's size
+  int dynamic_grid = 0;     // grid of the dynamic schedule: the occupancy limit, or (server jobs)
+                            // serving_grid
+  int serving_grid = 0;     // a grid for jobs that share the device (see setup_context)
   int cus = 0;
   uint32_t fallbacks_seen = 0;  // health[kHealthFallback] at the last check
   bool diagnostics = false; // collect per-wave counters in dataflow epochs
@@ -469,17 +471,20 @@ f2v_status setup_context(f2v_ctx* c, const f2v_params* p, const int64_t* d_rowpt
     if (x >= 64 && x <= (1ll << 30)) c->max_polls = static_cast<uint32_t>(x);
   }
   {
-    // The dynamic schedule (jobs sharing the device) gets one wave per group
-    // of about kDynamicLookahead batches, at most the occupancy limit: a
-    // batch's units can only run once the batches just before it are done,
-    // so more waves would mostly poll while other jobs need the CUs.
+    // The dynamic schedule runs a job alone on the occupancy limit (sbm4m:
+    // 12.7 ms against 25.3 with the grid below).  Jobs that share the device
+    // (the server's) get one wave per group of about kDynamicLookahead
+    // batches, at most the occupancy limit: a batch's units can only run once
+    // the batches just before it are done, so more waves would mostly poll
+    // while other jobs need the CUs.
     const int64_t slots = slots_of(c->var);
     const int64_t per_batch = (int64_t(p->batch) * 5 / 4 + slots - 1) / slots;  // units incl. splits
     const int64_t groups = kDynamicLookahead * per_batch;
     int64_t blocks = (groups + (kBlock / 64) - 1) / (kBlock / 64);
     if (blocks < 1) blocks = 1;
     if (blocks > c->update_grid) blocks = c->update_grid;
-    c->dynamic_grid = static_cast<int>(blocks);
+    c->serving_grid = static_cast<int>(blocks);
+    c->dynamic_grid = c->update_grid;
   }
   c->record_events = with_events;
   if (with_events)
@@ -1009,6 +1014,7 @@ const void* ctx_pack_fn(const f2v_ctx* c) {
   return c->p.d == c->var->g * c->var->v * c->var->r ? c->var->pack_full[fam] : c->var->pack[fam];
 }
 int ctx_dynamic_grid(const f2v_ctx* c) { return c->dynamic_grid; }
+void ctx_use_serving_grid(f2v_ctx* c) { c->dynamic_grid = c->serving_grid; }
 int ctx_schedule(const f2v_ctx* c) { return c->p.schedule; }
 // f2v_sync_embedding on another stream (the serving form's pack stream).
 hipError_t ctx_sync_embedding_on(f2v_ctx* c, hipStream_t st) {

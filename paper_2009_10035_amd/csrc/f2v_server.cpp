@@ -37,6 +37,7 @@ const uint32_t* ctx_vertex_words(const f2v_ctx* c);
 int64_t ctx_n(const f2v_ctx* c);
 const void* ctx_pack_fn(const f2v_ctx* c);
 int ctx_dynamic_grid(const f2v_ctx* c);
+void ctx_use_serving_grid(f2v_ctx* c);
 hipError_t ctx_sync_embedding_on(f2v_ctx* c, hipStream_t st);
 f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa, EpochArgs* A, int* next);
 void epoch_commit(f2v_ctx* c, int next);
@@ -384,6 +385,7 @@ f2v_status f2v_server_submit(f2v_server* s, const f2v_params* p, const int64_t* 
   j.cost = p->n * static_cast<int64_t>(p->d);
   // validates the CSR on the device (synchronises this slot's stream only)
   st = f2v_init(p, d_rowptr, d_colidx, d_z, d_ws, ws_bytes, s->streams[slot], &j.ctx);
+  if (st == F2V_OK) f2v::ctx_use_serving_grid(j.ctx);
   if (st != F2V_OK) return sfail(s, st, f2v_last_error(nullptr));
   f2v::ctx_set_record_events(j.ctx, false);
   s->slot_job[slot] = j.id;

@@ -898,6 +898,37 @@ __device__ __forceinline__ uint32_t join_static_launch(const EpochArgs& A, uint3
   }
 }
 
+// Dynamic-schedule instances: the waves of a workgroup take tickets from a
+// shared run of kGroupClaim consecutive tickets, one atomic on the job's
+// counter per run, so that consecutive units still go to different waves.
+// The LDS word holds (first ticket of the run << 32) | tickets taken.  The
+// wave that finds exactly kGroupClaim taken claims the next run and installs
+// it (taking its first ticket); a wave that finds more waits for that (one
+// global atomic and one LDS store away).  Tickets are taken in increasing
+// order, and a run's next ticket is taken as soon as any wave of the
+// workgroup has finished what it holds, so the lowest unfinished ticket is
+// always held by a running wave.  A wait that outlasts its bound raises the
+// error word and returns a ticket past every job's end.
+constexpr uint32_t kGroupClaim = 4;
+__device__ __forceinline__ uint32_t take_ticket(uint64_t* run, uint32_t* counter, uint32_t* err) {
+  for (uint32_t spin = 0;; ++spin) {
+    const uint64_t old = __hip_atomic_fetch_add(run, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t taken = static_cast<uint32_t>(old), base = static_cast<uint32_t>(old >> 32);
+    if (taken < kGroupClaim) return base + taken;
+    if (taken == kGroupClaim) {
+      const uint32_t b = atomicAdd(counter, kGroupClaim);
+      __hip_atomic_store(run, (static_cast<uint64_t>(b) << 32) | 1ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+      return b;
+    }
+    if (spin >= (1u << 20)) {
+      atomicOr(err, kErrWordWait);
+      return 0xffffffffu;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // MULTI: a launch over several jobs (P), each on its own range of workgroups
 // with its own EpochArgs; otherwise one job (A1).
 template <int G, int V, int R, bool BF16, bool FULL, int FAM, bool MULTI, bool STAGE = false, bool ROBUST = MULTI>
@@ -924,6 +955,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
   __shared__ std::conditional_t<STAGE, NegStage, uint32_t> stage_lds;
   if constexpr (STAGE) {
     if (threadIdx.x < 2) stage_lds.tag[threadIdx.x] = 0u;
+    __syncthreads();
+  }
+  // dynamic-schedule instances: the workgroup's run of claimed tickets, used
+  // up at the start (see take_ticket)
+  __shared__ uint64_t claim_run;
+  if constexpr (ROBUST) {
+    if (threadIdx.x == 0) claim_run = kGroupClaim;
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -968,7 +1006,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 64 && 
     int64_t t;
     if (claim) {
       uint32_t x = 0;
-      if (lane == 0) x = atomicAdd(A.ticket, 1u);
+      if (lane == 0) x = ROBUST ? take_ticket(&claim_run, A.ticket, A.err) : atomicAdd(A.ticket, 1u);
       t = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
     } else {
       t = static_cast<int64_t>(g) + nwaves;
