@@ -683,6 +683,14 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   sa.epoch = static_cast<uint32_t>(epoch);
   sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
   sa.err = c->at<uint32_t>(L.err);
+  // rows of 8 lanes are their own publication in the schedules that wait:
+  // the next buffer starts the epoch unwritten
+  const bool row_pub = slots == 8 && (p.schedule == F2V_SCHED_DATAFLOW || p.schedule == F2V_SCHED_DYNAMIC);
+  const int next_buf = 1 - c->cur;
+  sa.fill = row_pub ? (bf16 ? reinterpret_cast<uint32_t*>(c->bbuf[next_buf]) : reinterpret_cast<uint32_t*>(c->zbuf[next_buf]))
+                    : nullptr;
+  sa.fill_words = bf16 ? int64_t(p.n) * p.d / 2 : int64_t(p.n) * p.d;
+  sa.fill_word = bf16 ? f2v::kUnwrittenBf16Pair : f2v::kUnwritten;
   const f2v::Feistel f = f2v::make_feistel(p.n, p.seed, static_cast<uint32_t>(epoch));
   sa.feistel_half = f.half;
   sa.feistel_mask = f.mask;

@@ -10,6 +10,18 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
+// Rows of at most 16 elements (kernels of 8 lanes per row) are their own
+// publication.  Before an epoch that waits for earlier batches, the prologue
+// sets every 32-bit word of the next buffer to the unwritten pattern: the
+// signalling NaN 0x7f810000 in FP32 rows, two bf16 signalling NaNs 0x7f81 in
+// bf16 rows (which widen to the same FP32 bits).  No step stores either:
+// arithmetic returns quiet NaNs, and the bf16 rounding keeps a NaN quiet and
+// rounds no finite value to a NaN.  Every row is stored exactly once per
+// epoch, by aligned stores of 32 bits or more (bf16 rows have even d), so a
+// word read as anything but the pattern holds its final value.
+constexpr uint32_t kUnwritten = 0x7f810000u;
+constexpr uint32_t kUnwrittenBf16Pair = 0x7f817f81u;
+
 // Device error record of a context: word 0 has bit 0 set once a wait for a
 // vertex's publication exceeded its bound, bit 1 once a late unit's wait for
 // its row's early sum did.  Later epochs then do nothing (the update and the
@@ -197,6 +209,10 @@ struct SetupArgs {
   int32_t feistel_half;
   uint32_t feistel_mask;
   const uint32_t* err;      // the context's error record: set = do nothing (k_walks: may be nullptr)
+  uint32_t* fill;           // the next buffer, set to the unwritten pattern first (nullptr:
+                            // not needed)
+  int64_t fill_words;       // its size in 32-bit words (n * d, or n * d / 2 for bf16 rows)
+  uint32_t fill_word;       // kUnwritten or kUnwrittenBf16Pair
 };
 
 struct LossArgs {

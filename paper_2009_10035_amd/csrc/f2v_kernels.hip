@@ -492,6 +492,22 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
     st_coherent_u32(p + i, v);
 }
 
+// The next buffer before an epoch whose rows are their own publication:
+// every word set to the unwritten pattern (16-byte stores where they fit; the
+// buffer is 16-byte aligned).  The update kernel is the next on the stream.
+template <bool MULTI>
+__global__ void k_fill_unwritten(SetupArgs A1, const SetupArgs* tab) {
+  const SetupArgs& A = MULTI ? tab[blockIdx.y] : A1;
+  if (A.fill == nullptr || *A.err != 0u) return;
+  const int64_t quads = A.fill_words / 4;
+  const uint4 q = make_uint4(A.fill_word, A.fill_word, A.fill_word, A.fill_word);
+  uint4* p4 = reinterpret_cast<uint4*>(A.fill);
+  const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = t0; i < quads; i += stride) p4[i] = q;
+  if (t0 < A.fill_words - quads * 4) A.fill[quads * 4 + t0] = A.fill_word;
+}
+
 // CSR validation: bit 0 rowptr[0] != 0, bit 1 decreasing rowptr, bit 2
 // rowptr[n] != nnz, bit 3 a column index outside [0, n).
 __global__ void k_check_csr(const int64_t* rowptr, const int32_t* colidx, int64_t n, int64_t nnz,
@@ -788,7 +804,10 @@ int grid_for(int64_t work, int threads) {
 // value, the multi-job ones from the table (blockIdx.y = job).
 template <bool MULTI>
 void launch_prologue(const SetupArgs& one, const SetupArgs* d_tab, unsigned y, int64_t positions, int64_t walks,
-                     int64_t splits, int64_t batches, int batch_threads, int64_t tickets, hipStream_t st) {
+                     int64_t splits, int64_t batches, int batch_threads, int64_t tickets, int64_t fill_quads,
+                     hipStream_t st) {
+  if (fill_quads > 0)
+    hipLaunchKernelGGL(k_fill_unwritten<MULTI>, dim3(grid_for(fill_quads, 256), y), dim3(256), 0, st, one, d_tab);
   hipLaunchKernelGGL(k_setup_positions<MULTI>, dim3(grid_for(positions, 256), y), dim3(256), 0, st, one, d_tab);
   if (walks > 0) hipLaunchKernelGGL(k_walks<MULTI>, dim3(grid_for(walks, 256), y), dim3(256), 0, st, one, d_tab);
   if (splits > 0) {
@@ -811,7 +830,7 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t st) {
 // the largest need among the jobs; the kernels stride over their own job's
 // sizes, so the surplus blocks of a smaller job find nothing to do.
 hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int njobs, hipStream_t st) {
-  int64_t positions = 0, walks = 0, splits = 0, batches = 0, tickets = 0;
+  int64_t positions = 0, walks = 0, splits = 0, batches = 0, tickets = 0, fill_quads = 0;
   int batch_threads = 256;
   for (int j = 0; j < njobs; ++j) {
     const SetupArgs& a = h_tab[j];
@@ -822,13 +841,14 @@ hipError_t launch_setup_pack(const SetupArgs* d_tab, const SetupArgs* h_tab, int
     batches = std::max(batches, static_cast<int64_t>(a.nb));
     tickets = std::max(tickets, a.n + 2 * static_cast<int64_t>(a.nb) * a.slots);
     if (a.b >= 1024) batch_threads = 1024;
+    if (a.fill) fill_quads = std::max(fill_quads, (a.fill_words + 3) / 4);
   }
   const SetupArgs one = d_tab ? SetupArgs{} : h_tab[0];
   const unsigned y = static_cast<unsigned>(njobs);
   if (d_tab) {
-    launch_prologue<true>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, st);
+    launch_prologue<true>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, fill_quads, st);
   } else {
-    launch_prologue<false>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, st);
+    launch_prologue<false>(one, d_tab, y, positions, walks, splits, batches, batch_threads, tickets, fill_quads, st);
   }
   return hipGetLastError();
 }

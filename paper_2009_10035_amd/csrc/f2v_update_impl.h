@@ -13,9 +13,13 @@
 // Synchronous minibatch semantics on a device that overlaps batches.  The
 // epoch reads rows from `zc` (the state at the start of the epoch) and writes
 // every updated row once into `zn`.  A unit of batch k reading vertex x takes
-// zn[x] if x belongs to an earlier batch (after waiting until x's word shows it
-// published) and zc[x] otherwise, so every read sees exactly the state the
-// sequential algorithm has at the start of batch k.  Tickets are in batch
+// zn[x] if x belongs to an earlier batch (after waiting until it is published)
+// and zc[x] otherwise, so every read sees exactly the state the sequential
+// algorithm has at the start of batch k.  Rows of more than 16 elements are
+// published by x's word, stored once the row's stores have completed.  Rows of
+// at most 16 elements (8 lanes per row) are their own publication: the
+// prologue sets zn to a pattern that no step stores, and a reader re-reads a
+// row that still holds it (see RowPub).  Tickets are in batch
 // order, and inside a batch all whole and early units come before the late
 // units, in separate wave groups.  A unit waits only on units of earlier
 // batches, and a late unit also on early units of its own batch, all at lower
@@ -35,6 +39,16 @@ namespace f2v {
 // per lane at G = 8 (d = 2) left three waves per SIMD instead of four (the
 // d = 2 layout update on 2M vertices: 1.38 ms with eight, 1.21 with four,
 // 1.89 with two).
+// Rows of 8 lanes (d <= 16) are their own publication; wider rows are
+// published by the vertex's word.  Measured on the 2-D layout (d = 2, 2M
+// vertices): the update took 1.11-1.13 ms against 1.19 with the word.  For
+// d = 128 it was no faster in FP32 and slower in bf16 (whole rows re-read by
+// every poll), so those rows keep the word.
+template <int G>
+struct RowPub {
+  static constexpr bool value = G == 8;
+};
+
 template <int G>
 struct ListShape {
   static constexpr int kIdxPerLane = (64 / G) < 4 ? (64 / G) : 4;
@@ -76,13 +90,58 @@ __device__ __forceinline__ void poll_backoff(uint32_t polls) {
   else __builtin_amdgcn_s_sleep(16);
 }
 
-// Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published.
-// Bounded by a count of polls (A.max_polls; a suspended wave does not poll,
-// so a suspension cannot trip it): at the bound it raises the error word,
-// which makes every other waiter stop within 64 polls.  It also stops once
-// another wave has raised it.  (The give-up is kept to one atomic: naming
-// the awaited entry there costs the hot kernels registers, scratch and about
-// 10% more instructions.)
+// A row read from the next buffer: does the lane's part of it still hold the
+// unwritten pattern anywhere?
+template <int R, int V>
+__device__ __forceinline__ bool unwritten(const float (&y)[R][V]) {
+  bool u = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < V; ++i) u |= __float_as_uint(y[r][i]) == kUnwritten;
+  return u;
+}
+
+// Bookkeeping of a wait for rows of earlier batches, shared by the waits
+// below.  Bounded by a count of polls (A.max_polls; a suspended wave does not
+// poll, so a suspension cannot trip it): at the bound it raises the error
+// word, which makes every other waiter stop within 64 polls.  It also stops
+// once another wave has raised it.  Returns false to stop waiting.
+template <bool ROBUST>
+__device__ __forceinline__ bool wait_round(const EpochArgs& A, uint32_t& polls) {
+  if (ROBUST && polls == kLongPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
+  ++polls;
+  if ((polls & 63u) == 0) {
+    if (polls >= A.max_polls) {
+      if ((threadIdx.x & 63) == 0) atomicOr(A.err, kErrWordWait);
+      return false;
+    }
+    if (ld_coherent_u32(A.err) != 0) return false;
+  }
+  poll_backoff(polls);
+  return true;
+}
+
+template <bool ROBUST>
+__device__ __forceinline__ void wait_done(const EpochArgs& A, uint64_t t0, uint32_t polls, WaveCounters& wc) {
+  compiler_fence();
+  // the unit waited on the chain of publications: finish it ahead of waves
+  // doing work that nothing waits for yet
+  __builtin_amdgcn_s_setprio(2);
+  if (A.wave_stats) {
+    wc.wait += clock64() - t0;
+    wc.polls += polls;
+    wc.waits += 1;
+  }
+  if (A.trace) wc.last_wait_end = wall_clock64();
+}
+
+// Rows y[q] (vertices vid[q] >= 0 with chk[q]) just read from the next buffer
+// `src` with device-scope loads: re-read the lane's part of each one that
+// still holds the unwritten pattern until none does (the row has been
+// stored).  Each lane re-reads only its own words of the rows it lacks.
+// Wait until the listed vertices (vid[q] >= 0 with pend[q]) are published
+// (word publication).  Bounded as in wait_round.
 template <int U, bool ROBUST>
 __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t (&vid)[U],
                                                bool (&pend)[U], WaveCounters& wc) {
@@ -107,27 +166,9 @@ __device__ __forceinline__ void wait_published(const EpochArgs& A, const int32_t
       any |= pend[q];
     }
     if (!__any(any)) break;
-    if (ROBUST && polls == kLongPolls && (threadIdx.x & 63) == 0) atomicAdd(A.health + kHealthLongWait, 1u);
-    ++polls;
-    if ((polls & 63u) == 0) {
-      if (polls >= A.max_polls) {
-        if ((threadIdx.x & 63) == 0) atomicOr(A.err, kErrWordWait);
-        break;
-      }
-      if (ld_coherent_u32(A.err) != 0) break;
-    }
-    poll_backoff(polls);
+    if (!wait_round<ROBUST>(A, polls)) break;
   }
-  compiler_fence();
-  // the unit waited on the chain of publications: finish it ahead of waves
-  // doing work that nothing waits for yet
-  __builtin_amdgcn_s_setprio(2);
-  if (A.wave_stats) {
-    wc.wait += clock64() - t0;
-    wc.polls += polls;
-    wc.waits += 1;
-  }
-  if (A.trace) wc.last_wait_end = wall_clock64();
+  wait_done<ROBUST>(A, t0, polls, wc);
 }
 
 // Row elements owned by lane l of a group: R vectors of V at (r*G + l)*V.
@@ -148,6 +189,67 @@ __device__ __forceinline__ void load_row(const typename Elem<BF16>::T* base, int
       for (int i = 0; i < V; ++i) y[r][i] = 0.0f;
     }
   }
+}
+
+// A vertex index the compiler must take as new here: the wait's re-reads
+// recompute their addresses instead of keeping the first reads' addresses
+// live across the wait.
+template <int G>
+__device__ __forceinline__ int32_t opaque_index(int32_t v) {
+  if constexpr (G == 64) asm volatile("" : "+s"(v));
+  else asm volatile("" : "+v"(v));
+  return v;
+}
+
+// vid[q] for a lane-varying q (a select per entry, no indexed registers)
+template <int U>
+__device__ __forceinline__ int32_t pick(const int32_t (&vid)[U], int q) {
+  int32_t v = vid[0];
+#pragma unroll
+  for (int j = 1; j < U; ++j) v = q == j ? vid[j] : v;
+  return v;
+}
+
+// The wait of the rows whose bits are set in `lack` (per lane: rows of which
+// this lane's part still held the unwritten pattern): poll the lowest such
+// row's part until it is complete, then the next.  `incomplete(v)` re-reads
+// vertex v's part and tells whether it still lacks a word.  The rows' data is
+// read again by the caller once every part is complete.
+template <int U, bool ROBUST, typename F>
+__device__ __forceinline__ void wait_rows(const EpochArgs& A, const int32_t (&vid)[U], uint32_t lack,
+                                          WaveCounters& wc, F incomplete) {
+  const uint64_t t0 = A.wave_stats ? clock64() : 0;
+  uint32_t polls = 0;
+#pragma clang loop unroll(disable)
+  while (wait_round<ROBUST>(A, polls)) {
+    if (lack != 0u && !incomplete(opaque_index<64>(0) + pick<U>(vid, __builtin_ctz(lack)))) lack &= lack - 1u;
+    if (!__any(lack != 0u)) break;
+  }
+  wait_done<ROBUST>(A, t0, polls, wc);
+}
+
+// Rows y[q] (vertices vid[q] >= 0 with chk[q]) just read from the next buffer
+// `src` with device-scope loads: if any lane's part of one still holds the
+// unwritten pattern, wait until every such part is complete and read the
+// rows again.  kAll: every row with vid[q] >= 0 is checked (chk is that), so
+// the rows read again are all of them, a form that keeps fewer registers.
+template <int G, int V, int R, bool BF16, bool FULL, int U, bool ROBUST, bool kAll>
+__device__ __forceinline__ void await_rows(const EpochArgs& A, const typename Elem<BF16>::T* src,
+                                           const int32_t (&vid)[U], const bool (&chk)[U], int l,
+                                           float (&y)[U][R][V], WaveCounters& wc) {
+  uint32_t lack = 0;
+#pragma unroll
+  for (int q = 0; q < U; ++q) lack |= (chk[q] && vid[q] >= 0 && unwritten<R, V>(y[q])) ? (1u << q) : 0u;
+  if (!__any(lack != 0u)) return;
+  wait_rows<U, ROBUST>(A, vid, lack, wc, [&](int32_t v) {
+    float t[R][V];
+    load_row<G, V, R, BF16, FULL>(src, v, A.d, l, true, t);
+    return unwritten<R, V>(t);
+  });
+#pragma unroll
+  for (int q = 0; q < U; ++q)
+    if (vid[q] >= 0 && (kAll || chk[q]))
+      load_row<G, V, R, BF16, FULL>(src, opaque_index<G>(vid[q]), A.d, l, true, y[q]);
 }
 
 // Partial (per lane) dot product (sigmoid) or squared distance (Student-t).
@@ -269,7 +371,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait) wait_published<U, ROBUST>(A, vid, pend, wc);
+  if (kNext && wait && !RowPub<G>::value) wait_published<U, ROBUST>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -346,6 +448,8 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
         for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
     }
   }
+  if constexpr (RowPub<G>::value)
+    if (kNext && wait) await_rows<G, V, R, BF16, FULL, U, ROBUST, true>(A, src, vid, pend, l, y, wc);
   float dq[U];
 #pragma unroll
   for (int q = 0; q < U; ++q) dq[q] = pair_partial<R, V>(kForce, a, y[q]);
@@ -404,12 +508,14 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
       ent[i] = kEntNone;
       cur[i] = old[i] = rec[i] = false;
       if (valid) {
-        const uint32_t wd = ld_coherent_u32(A.word + v);
+        // (a row that is its own publication needs only the word's batch,
+        // fixed for the epoch: a cached load, and every such row is checked)
+        const uint32_t wd = RowPub<G>::value ? A.word[v] : ld_coherent_u32(A.word + v);
         const int32_t kb = static_cast<int32_t>(wd & ~kPublished);
         const bool from_next = kb < k;
         ent[i] = static_cast<uint32_t>(v) | (e >= len ? kEntRepulsive : 0u) |
                  (from_next ? kEntNext : 0u) |
-                 ((wait && from_next && (wd & kPublished) == 0u) ? kEntPending : 0u);
+                 ((wait && from_next && (RowPub<G>::value || (wd & kPublished) == 0u)) ? kEntPending : 0u);
         cur[i] = !from_next;
         rec[i] = from_next && kb >= k - A.late_window;
         old[i] = from_next && !rec[i];
@@ -556,12 +662,12 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
       for (int q = 0; q < UN; ++q) {
         pend[q] = nxt[q] = false;
         if (vid[q] >= 0) {
-          const uint32_t wd = ld_coherent_u32(A.word + vid[q]);
+          const uint32_t wd = RowPub<G>::value ? A.word[vid[q]] : ld_coherent_u32(A.word + vid[q]);
           nxt[q] = static_cast<int32_t>(wd & ~kPublished) < kw;
-          pend[q] = wait && nxt[q] && (wd & kPublished) == 0u;
+          pend[q] = wait && nxt[q] && (RowPub<G>::value || (wd & kPublished) == 0u);
         }
       }
-      if (wait) wait_published<UN, ROBUST>(A, vid, pend, wc);
+      if (wait && !RowPub<G>::value) wait_published<UN, ROBUST>(A, vid, pend, wc);
 #pragma unroll
       for (int q = 0; q < UN; ++q) {
         if (vid[q] >= 0) {
@@ -573,6 +679,8 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
             for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
         }
       }
+      if constexpr (RowPub<G>::value)
+        if (wait) await_rows<G, V, R, BF16, FULL, UN, ROBUST, false>(A, zn, vid, pend, l, y, wc);
       if (mode == 2 && writer) {
 #pragma unroll
         for (int q = 0; q < UN; ++q)
@@ -836,7 +944,9 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   // the step of Eq. 10 and its publication
   const bool finish = active && !early;
   const uint64_t tp = A.wave_stats ? clock64() : 0;
-  if (finish) {
+  // (a held vertex, a failure drill: its word is never set; a row that is its
+  // own publication is not stored either)
+  if (finish && (!RowPub<G>::value || u != A.hold)) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e0 = (r * G + l) * V;
@@ -856,7 +966,9 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
       }
     }
   }
-  drain_memory();
+  // the word publishes the row once its stores have completed; a row that is
+  // its own publication has the word as a record for the post-mortem only
+  if constexpr (!RowPub<G>::value) drain_memory();
   if (finish && l == 0 && u != A.hold) st_coherent_u32(A.word + u, static_cast<uint32_t>(w.k) | kPublished);
   if (A.trace && finish && l == 0) {
     A.trace[2 * static_cast<int64_t>(u)] = static_cast<uint32_t>(wc.last_wait_end);

@@ -24,9 +24,9 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def held_case():
+def held_case(d=32):
     g = gg.erdos_renyi(3000, 12.0, 1)
-    p = dict(d=32, batch=128, s=5, force="sigmoid", lr0=0.02, seed=11)
+    p = dict(d=d, batch=128, s=5, force="sigmoid", lr0=0.02, seed=11)
     # the vertex at position 0 of epoch 0 is in batch 0: its neighbours in
     # later batches wait for its row
     v = int(oracle.partition(g.n, p["seed"], 0)[0])
@@ -34,9 +34,12 @@ def held_case():
     return g, p, v
 
 
-@pytest.mark.parametrize("schedule", ["dataflow", "dynamic"])
-def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule):
-    g, p, v = held_case()
+# d = 32: the row is published by its vertex word, which the hold keeps unset;
+# d = 2 (8 lanes per row): the row is its own publication, and the hold keeps
+# it unstored
+@pytest.mark.parametrize("schedule,d", [("dataflow", 32), ("dynamic", 32), ("dataflow", 2), ("dynamic", 2)])
+def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule, d):
+    g, p, v = held_case(d)
     monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
     monkeypatch.setenv("F2V_WAIT_POLLS", "4096")
     rowptr, colidx = device_graph(g)
