@@ -213,9 +213,10 @@ f2v_status f2v_sync_embedding(f2v_ctx *ctx);
  * later epochs of the context do nothing until this check, so the failed
  * epoch's vertex words are kept: f2v_last_error then gives how many vertices
  * were never published and the earliest of them.  (In the dataflow and
- * dynamic schedules, rows of d <= 16 elements are their own publication: the
- * next buffer is first set to a signalling-NaN pattern, so after a failed
- * epoch the rows it never stored hold that pattern.)  If a dataflow launch since
+ * dynamic schedules, narrow rows are their own publication: FP32 rows of
+ * d <= 64 with d even or d <= 32, bf16 rows of d <= 32.  The next buffer is
+ * first set to a signalling-NaN pattern, so after a failed epoch the rows it
+ * never stored hold that pattern.)  If a dataflow launch since
  * the last check found its grid not co-resident, later epochs use one block
  * per CU fewer. */
 f2v_status f2v_check(f2v_ctx *ctx);
@@ -268,8 +269,8 @@ f2v_status f2v_negatives(int64_t n, int32_t batch, int32_t s, uint64_t seed, int
  * Algorithm 1 on a device whose XCDs have caches that are not coherent with
  * each other).  `pairs` pairs of single-wave workgroups, writer and reader
  * on different XCDs, run `rounds` rounds: the writer publishes a 512-byte
- * row exactly as the update kernel publishes an updated row of more than 16
- * elements, and a split row's early sum (device-scope
+ * row exactly as the update kernel publishes a wide updated row (d = 128)
+ * and a split row's early sum (device-scope
  * row stores, wait for their completion, device-scope flag store), the
  * reader polls the flag and reads the row as a dependent unit does, checks
  * every word, and acknowledges.  1 <= pairs <= 1024, 1 <= rounds <= 2^24.

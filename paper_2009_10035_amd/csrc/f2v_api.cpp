@@ -683,9 +683,11 @@ f2v_status epoch_prepare(f2v_ctx* c, int32_t epoch, SetupArgs* sa_out, EpochArgs
   sa.epoch = static_cast<uint32_t>(epoch);
   sa.identity = p.perm_mode == F2V_PERM_IDENTITY;
   sa.err = c->at<uint32_t>(L.err);
-  // rows of 8 lanes are their own publication in the schedules that wait:
-  // the next buffer starts the epoch unwritten
-  const bool row_pub = slots == 8 && (p.schedule == F2V_SCHED_DATAFLOW || p.schedule == F2V_SCHED_DYNAMIC);
+  // rows of up to 16 lanes, and FP32 rows of 32, are their own publication in
+  // the schedules that wait (RowPub in the update kernel): the next buffer
+  // starts the epoch unwritten
+  const bool row_pub = (slots >= 4 || (slots == 2 && !bf16)) &&
+                       (p.schedule == F2V_SCHED_DATAFLOW || p.schedule == F2V_SCHED_DYNAMIC);
   const int next_buf = 1 - c->cur;
   sa.fill = row_pub ? (bf16 ? reinterpret_cast<uint32_t*>(c->bbuf[next_buf]) : reinterpret_cast<uint32_t*>(c->zbuf[next_buf]))
                     : nullptr;

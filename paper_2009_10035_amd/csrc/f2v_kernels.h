@@ -10,8 +10,8 @@ namespace f2v {
 // once the batch that updates it has published its new row.
 constexpr uint32_t kPublished = 0x80000000u;
 
-// Rows of at most 16 elements (kernels of 8 lanes per row) are their own
-// publication.  Before an epoch that waits for earlier batches, the prologue
+// Rows of the kernels of up to 16 lanes per row, and FP32 rows of 32 lanes,
+// are their own publication.  Before an epoch that waits for earlier batches, the prologue
 // sets every 32-bit word of the next buffer to the unwritten pattern: the
 // signalling NaN 0x7f810000 in FP32 rows, two bf16 signalling NaNs 0x7f81 in
 // bf16 rows (which widen to the same FP32 bits).  No step stores either:

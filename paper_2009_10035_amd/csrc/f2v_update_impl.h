@@ -39,14 +39,16 @@ namespace f2v {
 // per lane at G = 8 (d = 2) left three waves per SIMD instead of four (the
 // d = 2 layout update on 2M vertices: 1.38 ms with eight, 1.21 with four,
 // 1.89 with two).
-// Rows of 8 lanes (d <= 16) are their own publication; wider rows are
-// published by the vertex's word.  Measured on the 2-D layout (d = 2, 2M
-// vertices): the update took 1.11-1.13 ms against 1.19 with the word.  For
-// d = 128 it was no faster in FP32 and slower in bf16 (whole rows re-read by
-// every poll), so those rows keep the word.
-template <int G>
+// Rows of up to 16 lanes, and FP32 rows of 32 lanes, are their own
+// publication; the others are published by the vertex's word.  Update times
+// with the word -> with the row (Chung-Lu 1M FP32, dataflow; SBM 4M bf16,
+// dynamic): d = 2 on the 2-D layout 1.19 -> 1.12 ms; d = 32 FP32 4.49 ->
+// 3.22, bf16 9.63 -> 9.38; d = 64 FP32 3.28 -> 2.71, bf16 13.17 -> 13.46;
+// d = 128 FP32 3.05 -> 3.10, bf16 12.78 -> 14.64 (wide rows re-read whole by
+// every poll).
+template <int G, bool BF16>
 struct RowPub {
-  static constexpr bool value = G == 8;
+  static constexpr bool value = G <= 16 || (G == 32 && !BF16);
 };
 
 template <int G>
@@ -371,7 +373,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
     pend[q] = kNext && vid[q] >= 0 && (e & kEntPending) != 0u;
     rep[q] = (e & kEntRepulsive) != 0u;
   }
-  if (kNext && wait && !RowPub<G>::value) wait_published<U, ROBUST>(A, vid, pend, wc);
+  if (kNext && wait && !RowPub<G, BF16>::value) wait_published<U, ROBUST>(A, vid, pend, wc);
   if constexpr (BF16 && V == 2 && G >= 16 && U == 16) {
     // bf16 rows kept packed (one dword per lane and row) and widened at each
     // use, so that twice as many rows fit in the registers
@@ -448,7 +450,7 @@ __device__ __forceinline__ void accumulate_batch(const EpochArgs& A, const uint3
         for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
     }
   }
-  if constexpr (RowPub<G>::value)
+  if constexpr (RowPub<G, BF16>::value)
     if (kNext && wait) await_rows<G, V, R, BF16, FULL, U, ROBUST, true>(A, src, vid, pend, l, y, wc);
   float dq[U];
 #pragma unroll
@@ -510,12 +512,12 @@ __device__ __forceinline__ void accumulate_unit(const EpochArgs& A, bool active,
       if (valid) {
         // (a row that is its own publication needs only the word's batch,
         // fixed for the epoch: a cached load, and every such row is checked)
-        const uint32_t wd = RowPub<G>::value ? A.word[v] : ld_coherent_u32(A.word + v);
+        const uint32_t wd = RowPub<G, BF16>::value ? A.word[v] : ld_coherent_u32(A.word + v);
         const int32_t kb = static_cast<int32_t>(wd & ~kPublished);
         const bool from_next = kb < k;
         ent[i] = static_cast<uint32_t>(v) | (e >= len ? kEntRepulsive : 0u) |
                  (from_next ? kEntNext : 0u) |
-                 ((wait && from_next && (RowPub<G>::value || (wd & kPublished) == 0u)) ? kEntPending : 0u);
+                 ((wait && from_next && (RowPub<G, BF16>::value || (wd & kPublished) == 0u)) ? kEntPending : 0u);
         cur[i] = !from_next;
         rec[i] = from_next && kb >= k - A.late_window;
         old[i] = from_next && !rec[i];
@@ -662,12 +664,12 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
       for (int q = 0; q < UN; ++q) {
         pend[q] = nxt[q] = false;
         if (vid[q] >= 0) {
-          const uint32_t wd = RowPub<G>::value ? A.word[vid[q]] : ld_coherent_u32(A.word + vid[q]);
+          const uint32_t wd = RowPub<G, BF16>::value ? A.word[vid[q]] : ld_coherent_u32(A.word + vid[q]);
           nxt[q] = static_cast<int32_t>(wd & ~kPublished) < kw;
-          pend[q] = wait && nxt[q] && (RowPub<G>::value || (wd & kPublished) == 0u);
+          pend[q] = wait && nxt[q] && (RowPub<G, BF16>::value || (wd & kPublished) == 0u);
         }
       }
-      if (wait && !RowPub<G>::value) wait_published<UN, ROBUST>(A, vid, pend, wc);
+      if (wait && !RowPub<G, BF16>::value) wait_published<UN, ROBUST>(A, vid, pend, wc);
 #pragma unroll
       for (int q = 0; q < UN; ++q) {
         if (vid[q] >= 0) {
@@ -679,7 +681,7 @@ __device__ __forceinline__ void accumulate_negatives(const EpochArgs& A, bool ha
             for (int i = 0; i < V; ++i) y[q][r][i] = 0.0f;
         }
       }
-      if constexpr (RowPub<G>::value)
+      if constexpr (RowPub<G, BF16>::value)
         if (wait) await_rows<G, V, R, BF16, FULL, UN, ROBUST, false>(A, zn, vid, pend, l, y, wc);
       if (mode == 2 && writer) {
 #pragma unroll
@@ -946,7 +948,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   const uint64_t tp = A.wave_stats ? clock64() : 0;
   // (a held vertex, a failure drill: its word is never set; a row that is its
   // own publication is not stored either)
-  if (finish && (!RowPub<G>::value || u != A.hold)) {
+  if (finish && (!RowPub<G, BF16>::value || u != A.hold)) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e0 = (r * G + l) * V;
@@ -968,7 +970,7 @@ __device__ __forceinline__ void process_unit(const EpochArgs& A, const Unit& w, 
   }
   // the word publishes the row once its stores have completed; a row that is
   // its own publication has the word as a record for the post-mortem only
-  if constexpr (!RowPub<G>::value) drain_memory();
+  if constexpr (!RowPub<G, BF16>::value) drain_memory();
   if (finish && l == 0 && u != A.hold) st_coherent_u32(A.word + u, static_cast<uint32_t>(w.k) | kPublished);
   if (A.trace && finish && l == 0) {
     A.trace[2 * static_cast<int64_t>(u)] = static_cast<uint32_t>(wc.last_wait_end);

@@ -34,10 +34,10 @@ def held_case(d=32):
     return g, p, v
 
 
-# d = 32: the row is published by its vertex word, which the hold keeps unset;
-# d = 2 (8 lanes per row): the row is its own publication, and the hold keeps
-# it unstored
-@pytest.mark.parametrize("schedule,d", [("dataflow", 32), ("dynamic", 32), ("dataflow", 2), ("dynamic", 2)])
+# d = 128: the row is published by its vertex word, which the hold keeps
+# unset; d = 2 and 32 (8 and 16 lanes per row): the row is its own
+# publication, and the hold keeps it unstored
+@pytest.mark.parametrize("schedule,d", [("dataflow", 128), ("dynamic", 128), ("dataflow", 2), ("dynamic", 32)])
 def test_withheld_publication_times_out_and_is_named(monkeypatch, schedule, d):
     g, p, v = held_case(d)
     monkeypatch.setenv("F2V_HOLD_VERTEX", str(v))
